@@ -1,0 +1,198 @@
+"""ctypes binding of libpst.so: the C-ABI entry points under the same names.
+
+Only argument marshalling happens here; every step of the computation runs
+in the library's HIP kernels.  Device memory and streams come from PyTorch:
+fields are torch tensors on the GPU, passed by data pointer, and a plan runs
+on the torch stream that was current when it was created (or the one given).
+
+Importing this module fails with ImportError if libpst.so has not been
+built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpst.so")
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_1206_3215_amd.build`")
+lib = C.CDLL(_LIB_PATH)
+
+# enums (include/pst.h)
+PST_OK, PST_ERR_INVALID, PST_ERR_UNSUPPORTED, PST_ERR_OOM, PST_ERR_DEVICE, \
+    PST_ERR_NOT_CONVERGED, PST_ERR_NONFINITE = range(7)
+STATUS_NAMES = ["OK", "INVALID", "UNSUPPORTED", "OOM", "DEVICE", "NOT_CONVERGED", "NONFINITE"]
+PST_FP32, PST_FP64 = 0, 1
+PST_C2C, PST_R2C = 0, 1
+PST_NLS, PST_SG, PST_NS = 0, 1, 2
+PASS_NLS_ROW, PASS_NLS_COL, PASS_SG_ROW, PASS_SG_COL, PASS_NS_ROW, PASS_NS_COL = range(6)
+EQ = {"nls": PST_NLS, "sg": PST_SG, "ns": PST_NS}
+
+
+class Domain(C.Structure):
+    _fields_ = [("lx", C.c_double), ("ly", C.c_double), ("x0", C.c_double), ("y0", C.c_double)]
+
+
+class NlsParams(C.Structure):
+    _fields_ = [("d", Domain), ("dt", C.c_double), ("g", C.c_double)]
+
+
+class SgParams(C.Structure):
+    _fields_ = [("d", Domain), ("dt", C.c_double)]
+
+
+class NsParams(C.Structure):
+    _fields_ = [("d", Domain), ("dt", C.c_double), ("nu", C.c_double), ("tol", C.c_double),
+                ("max_iter", C.c_int), ("fixed_iters", C.c_int)]
+
+
+class Request(C.Structure):
+    _fields_ = [("eq", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("prec", C.c_int),
+                ("nsteps", C.c_int), ("params", C.c_void_p), ("f0", C.c_void_p),
+                ("f1", C.c_void_p), ("dev_status", C.c_void_p)]
+
+
+_vp = C.c_void_p
+_SIGS = {
+    "fft2d_plan": [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, C.POINTER(_vp)],
+    "pst_workspace_size": [_vp, C.POINTER(C.c_size_t)],
+    "pst_set_workspace": [_vp, _vp, C.c_size_t],
+    "fft2d_exec": [_vp, _vp, _vp, C.c_int],
+    "fft2d_destroy": [_vp],
+    "nls_step": [_vp, _vp, C.POINTER(NlsParams), C.c_int],
+    "sg_start": [_vp, _vp, _vp, _vp, _vp, C.POINTER(SgParams)],
+    "sg_step": [_vp, _vp, _vp, C.POINTER(SgParams), C.c_int],
+    "ns_step": [_vp, _vp, C.POINTER(NsParams), C.c_int, _vp],
+    "conserved_quantities": [_vp, C.c_int, _vp, _vp, _vp, C.POINTER(C.c_double)],
+    "pst_sync_status": [_vp, C.POINTER(C.c_int)],
+    "solve_batch": [C.POINTER(Request), C.c_int, _vp],
+    "pst_profile_enable": [_vp, C.c_int],
+    "pst_profile_read": [_vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)],
+    "pst_last_error": [],
+    "pst_version": [],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.argtypes = _args
+    _f.restype = C.c_char_p if _name in ("pst_last_error", "pst_version") else C.c_int
+
+
+class PstError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = lib.pst_last_error().decode()
+        super().__init__(f"{where}: {STATUS_NAMES[status] if 0 <= status < 7 else status}: {msg}")
+
+
+def check(status: int, where: str) -> None:
+    if status != PST_OK:
+        raise PstError(status, where)
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("field must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError("field must be contiguous")
+    return t.data_ptr()
+
+
+def domain(d) -> Domain:
+    return Domain(float(d.lx), float(d.ly), float(d.x0), float(d.y0))
+
+
+class Plan:
+    """Owns a pst_plan and its torch-allocated workspace."""
+
+    def __init__(self, nx: int, ny: int, kind: int = PST_C2C, prec: int = PST_FP32,
+                 batch: int = 1, stream=None):
+        import torch
+        self.nx, self.ny, self.kind, self.prec, self.batch = nx, ny, kind, prec, batch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = _vp()
+        check(lib.fft2d_plan(nx, ny, kind, prec, batch, _vp(self.stream.cuda_stream), C.byref(h)),
+              "fft2d_plan")
+        self.handle = h
+        n = C.c_size_t()
+        check(lib.pst_workspace_size(h, C.byref(n)), "pst_workspace_size")
+        self.workspace = torch.empty(max(int(n.value), 256), dtype=torch.uint8, device="cuda")
+        check(lib.pst_set_workspace(h, _vp(self.workspace.data_ptr()), n.value), "pst_set_workspace")
+
+    @property
+    def real_dtype(self):
+        import torch
+        return torch.float32 if self.prec == PST_FP32 else torch.float64
+
+    @property
+    def complex_dtype(self):
+        import torch
+        return torch.complex64 if self.prec == PST_FP32 else torch.complex128
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.fft2d_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- entry points -----------------------------------------------------
+    def fft2d_exec(self, inp, out, sign: int) -> None:
+        check(lib.fft2d_exec(self.handle, _ptr(inp), _ptr(out), sign), "fft2d_exec")
+
+    def nls_step(self, psi, d, dt: float, g: float, nsteps: int) -> None:
+        p = NlsParams(domain(d), dt, g)
+        check(lib.nls_step(self.handle, _ptr(psi), C.byref(p), nsteps), "nls_step")
+
+    def sg_start(self, u0, v0, u_prev, u_curr, d, dt: float) -> None:
+        p = SgParams(domain(d), dt)
+        check(lib.sg_start(self.handle, _ptr(u0), _ptr(v0), _ptr(u_prev), _ptr(u_curr), C.byref(p)),
+              "sg_start")
+
+    def sg_step(self, u_prev, u_curr, d, dt: float, nsteps: int) -> None:
+        p = SgParams(domain(d), dt)
+        check(lib.sg_step(self.handle, _ptr(u_prev), _ptr(u_curr), C.byref(p), nsteps), "sg_step")
+
+    def ns_step(self, omega, d, dt: float, nu: float, nsteps: int, tol: float = 1e-10,
+                max_iter: int = 50, fixed_iters: int = 0, dev_iters=None) -> None:
+        p = NsParams(domain(d), dt, nu, tol, max_iter, fixed_iters)
+        check(lib.ns_step(self.handle, _ptr(omega), C.byref(p), nsteps, _ptr(dev_iters)), "ns_step")
+
+    def conserved_quantities(self, eq: str, f0, f1=None, d=None, dt: float = 0.0, g: float = 1.0,
+                             nu: float = 0.0) -> np.ndarray:
+        out = np.zeros(4 * self.batch, dtype=np.float64)
+        if eq == "nls":
+            p = NlsParams(domain(d), dt, g)
+        elif eq == "sg":
+            p = SgParams(domain(d), dt)
+        else:
+            p = NsParams(domain(d), dt, nu, 0.0, 1, 0)
+        st = lib.conserved_quantities(self.handle, EQ[eq], _ptr(f0), _ptr(f1), C.byref(p),
+                                      out.ctypes.data_as(C.POINTER(C.c_double)))
+        check(st, "conserved_quantities")
+        return out.reshape(self.batch, 4)
+
+    def profile_enable(self, on: bool = True) -> None:
+        check(lib.pst_profile_enable(self.handle, int(on)), "pst_profile_enable")
+
+    def profile_read(self, pass_id: int):
+        """(total_ms, launches) recorded for a pass since the last read."""
+        ms, n = C.c_double(), C.c_int()
+        check(lib.pst_profile_read(self.handle, pass_id, C.byref(ms), C.byref(n)), "pst_profile_read")
+        return ms.value, n.value
+
+    def sync_status(self) -> int:
+        s = C.c_int()
+        check(lib.pst_sync_status(self.handle, C.byref(s)), "pst_sync_status")
+        return s.value
+
+
+def version() -> str:
+    return lib.pst_version().decode()

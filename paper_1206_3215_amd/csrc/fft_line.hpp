@@ -1,0 +1,264 @@
+// Register/LDS Stockham FFT of one line, executed cooperatively by the
+// N/R threads that own it (gfx950, wave64).
+//
+// Layout.  Thread t (0 <= t < N/R) of a line owns R complex values
+// v[s] = x[t + s*(N/R)], s = 0..R-1.  Every stage reads its butterfly
+// inputs from exactly these positions, so the first stage loads straight
+// from global memory with unit stride across the wave, and after the last
+// stage v[s] holds X[t + s*(N/R)] in natural order, stored back the same
+// way.  Between stages the outputs go through LDS (Stockham autosort: a
+// radix-r butterfly j with k = j mod Ns writes its outputs to
+// (j/Ns)*Ns*r + k + q*Ns).  N = f * R^m with the odd-sized radix f (if any)
+// first; a stage of radix r < R runs R/r butterflies per thread.
+//
+// Twiddles of stage s (radix r, Ns = product of earlier radices) are read
+// from a table of (r-1)*Ns entries, entry (q-1)*Ns + k = exp(-2 pi i q k /
+// (Ns r)), computed in double precision on the host and rounded once.  The
+// inverse transform multiplies by their conjugates.  Transforms are
+// unnormalised: forward kernel exp(-i...), inverse exp(+i...).
+#pragma once
+
+#include <type_traits>
+
+#include "pst_common.hpp"
+
+namespace pst {
+
+// ---------------------------------------------------------------- stages ---
+__host__ __device__ constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
+
+__host__ __device__ constexpr int line_radix(int N) { return N < 16 ? N : 16; }
+
+// Radix of the first stage (the leftover factor, or R if N is a power of R).
+__host__ __device__ constexpr int first_radix(int N, int R) {
+  return (ilog2c(N) % ilog2c(R)) == 0 ? R : (1 << (ilog2c(N) % ilog2c(R)));
+}
+__host__ __device__ constexpr int num_stages(int N, int R) {
+  return (ilog2c(N) + ilog2c(R) - 1) / ilog2c(R);
+}
+__host__ __device__ constexpr int stage_radix(int N, int R, int s) {
+  return s == 0 ? first_radix(N, R) : R;
+}
+__host__ __device__ constexpr int stage_ns(int N, int R, int s) {
+  int ns = 1;
+  for (int i = 0; i < s; ++i) ns *= stage_radix(N, R, i);
+  return ns;
+}
+// Offset of stage s's twiddles in the per-length table.
+__host__ __device__ constexpr int stage_tw_offset(int N, int R, int s) {
+  int off = 0;
+  for (int i = 1; i < s; ++i) off += (stage_radix(N, R, i) - 1) * stage_ns(N, R, i);
+  return off;
+}
+__host__ __device__ constexpr int twiddle_table_len(int N) {
+  return stage_tw_offset(N, line_radix(N), num_stages(N, line_radix(N)));
+}
+
+// LDS slots of one line: one pad slot every 16 elements against bank conflicts.
+__host__ __device__ constexpr int lds_line_len(int N) { return N + N / 16 + 1; }
+__device__ __forceinline__ int lds_idx(int e) { return e + (e >> 4); }
+
+// ----------------------------------------------------------- butterflies ---
+// Multiply by exp(-+ 2 pi i m / 16) with compile-time m; INV selects +.
+//
+// Single precision writes the rotation as v + v*(w - 1) with w in the first
+// octant (angle pi/8 or pi/4) and the remaining multiple of pi/2 applied as
+// an exact quarter turn.  The float pair (cos - 1, sin) below was chosen so
+// that |w|^2 differs from 1 by ~1e-9 (the nearest floats of cos and sin give
+// ~5e-8), so repeated transforms do not shrink or grow the field's norm.
+struct Oct16f {
+  static constexpr float A1 = -0x1.37ca18p-4f;  // cos(pi/8) - 1
+  static constexpr float S1 = 0x1.87de2ap-2f;   // sin(pi/8)
+  static constexpr float A2 = -0x1.2bec32p-2f;  // cos(pi/4) - 1
+  static constexpr float S2 = 0x1.6a09e6p-1f;   // sin(pi/4)
+};
+
+// v * (1 + a + i s)
+__host__ __device__ __forceinline__ cpx<float> rot_near1(cpx<float> v, float a, float s) {
+  return cpx<float>{v.re + (v.re * a - v.im * s), v.im + (v.im * a + v.re * s)};
+}
+
+// v * (-i)^q (forward) or v * i^q (inverse)
+template <bool INV, int Q, typename T>
+__host__ __device__ __forceinline__ cpx<T> quarter(cpx<T> a) {
+  constexpr int q = ((INV ? -Q : Q) % 4 + 4) % 4;  // number of -i factors
+  if constexpr (q == 0) return a;
+  else if constexpr (q == 1) return cpx<T>{a.im, -a.re};
+  else if constexpr (q == 2) return cpx<T>{-a.re, -a.im};
+  else return cpx<T>{-a.im, a.re};
+}
+
+template <bool INV, int M, typename T>
+__host__ __device__ __forceinline__ cpx<T> rot16(cpx<T> a) {
+  constexpr int m = ((M % 16) + 16) % 16;
+  if constexpr (std::is_same<T, float>::value) {
+    constexpr int r = m & 3;
+    // forward W^m = exp(-2 pi i m/16): sign of the first-octant angle's sine
+    constexpr float sg = INV ? 1.0f : -1.0f;
+    if constexpr (r == 0) {
+      return quarter<INV, m / 4>(a);
+    } else if constexpr (r == 1) {
+      return quarter<INV, m / 4>(rot_near1(a, Oct16f::A1, sg * Oct16f::S1));
+    } else if constexpr (r == 2) {
+      return quarter<INV, m / 4>(rot_near1(a, Oct16f::A2, sg * Oct16f::S2));
+    } else {
+      // W^m = W^{4(q+1)} W^{-1}
+      return quarter<INV, m / 4 + 1>(rot_near1(a, Oct16f::A1, -sg * Oct16f::S1));
+    }
+  } else {
+    if constexpr (m % 4 == 0) {
+      return quarter<INV, m / 4>(a);
+    } else {
+      const T c = (T)cos16(m);
+      const T s = INV ? (T)sin16(m) : -(T)sin16(m);
+      return cpx<T>{a.re * c - a.im * s, a.re * s + a.im * c};
+    }
+  }
+}
+
+template <bool INV, typename T>
+__host__ __device__ __forceinline__ void dft2(cpx<T>& a, cpx<T>& b) {
+  cpx<T> t = a;
+  a = t + b;
+  b = t - b;
+}
+
+// In place: v[0..3] -> X[0..3].
+template <bool INV, typename T>
+__host__ __device__ __forceinline__ void dft4(cpx<T>& x0, cpx<T>& x1, cpx<T>& x2, cpx<T>& x3) {
+  cpx<T> a0 = x0 + x2, a1 = x0 - x2, a2 = x1 + x3, a3 = x1 - x3;
+  // forward: X1 = a1 - i a3, X3 = a1 + i a3
+  cpx<T> ia3 = cpx<T>{-a3.im, a3.re};
+  x0 = a0 + a2;
+  x2 = a0 - a2;
+  if (INV) {
+    x1 = a1 + ia3;
+    x3 = a1 - ia3;
+  } else {
+    x1 = a1 - ia3;
+    x3 = a1 + ia3;
+  }
+}
+
+template <bool INV, typename T>
+__host__ __device__ __forceinline__ void dft8(cpx<T>* v) {
+  // even/odd split: E = DFT4(x0,x2,x4,x6), O = DFT4(x1,x3,x5,x7)
+  dft4<INV>(v[0], v[2], v[4], v[6]);
+  dft4<INV>(v[1], v[3], v[5], v[7]);
+  cpx<T> o1 = rot16<INV, 2>(v[3]), o2 = rot16<INV, 4>(v[5]), o3 = rot16<INV, 6>(v[7]);
+  cpx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6], o0 = v[1];
+  v[0] = e0 + o0; v[4] = e0 - o0;
+  v[1] = e1 + o1; v[5] = e1 - o1;
+  v[2] = e2 + o2; v[6] = e2 - o2;
+  v[3] = e3 + o3; v[7] = e3 - o3;
+}
+
+template <bool INV, typename T>
+__host__ __device__ __forceinline__ void dft16(cpx<T>* v) {
+  // n = 4 n1 + n2, k = k1 + 4 k2:  DFT4 over n1, twiddle W16^(n2 k1), DFT4 over n2.
+  dft4<INV>(v[0], v[4], v[8], v[12]);
+  dft4<INV>(v[1], v[5], v[9], v[13]);
+  dft4<INV>(v[2], v[6], v[10], v[14]);
+  dft4<INV>(v[3], v[7], v[11], v[15]);
+  // now v[n2 + 4 k1] = Y[n2][k1]
+  v[5] = rot16<INV, 1>(v[5]);
+  v[9] = rot16<INV, 2>(v[9]);
+  v[13] = rot16<INV, 3>(v[13]);
+  v[6] = rot16<INV, 2>(v[6]);
+  v[10] = rot16<INV, 4>(v[10]);
+  v[14] = rot16<INV, 6>(v[14]);
+  v[7] = rot16<INV, 3>(v[7]);
+  v[11] = rot16<INV, 6>(v[11]);
+  v[15] = rot16<INV, 9>(v[15]);
+  dft4<INV>(v[0], v[1], v[2], v[3]);
+  dft4<INV>(v[4], v[5], v[6], v[7]);
+  dft4<INV>(v[8], v[9], v[10], v[11]);
+  dft4<INV>(v[12], v[13], v[14], v[15]);
+  // v[n2 + 4 k1] now holds X[k1 + 4 n2]: transpose the 4x4 index grid.
+  cpx<T> t;
+  t = v[1]; v[1] = v[4]; v[4] = t;
+  t = v[2]; v[2] = v[8]; v[8] = t;
+  t = v[3]; v[3] = v[12]; v[12] = t;
+  t = v[6]; v[6] = v[9]; v[9] = t;
+  t = v[7]; v[7] = v[13]; v[13] = t;
+  t = v[11]; v[11] = v[14]; v[14] = t;
+}
+
+template <int r, bool INV, typename T>
+__host__ __device__ __forceinline__ void dft(cpx<T>* v) {
+  if constexpr (r == 2) {
+    dft2<INV>(v[0], v[1]);
+  } else if constexpr (r == 4) {
+    dft4<INV>(v[0], v[1], v[2], v[3]);
+  } else if constexpr (r == 8) {
+    dft8<INV>(v);
+  } else if constexpr (r == 16) {
+    dft16<INV>(v);
+  }
+}
+
+// ------------------------------------------------------------ line FFT ---
+// One Stockham stage for thread t; outputs either stay in registers (last
+// stage) or are scattered to the line's LDS buffer.
+template <int N, int S, bool INV, typename T>
+__device__ __forceinline__ void line_stage(cpx<T> (&v)[line_radix(N)], cpx<T>* lds, int t,
+                                           const cpx<T>* __restrict__ tw) {
+  constexpr int R = line_radix(N);
+  constexpr int TL = N / R;
+  constexpr int r = stage_radix(N, R, S);
+  constexpr int Ns = stage_ns(N, R, S);
+  constexpr int B = R / r;
+  constexpr bool last = (S == num_stages(N, R) - 1);
+  constexpr int toff = stage_tw_offset(N, R, S);
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int j = t + b * TL;
+    cpx<T> w[r];
+#pragma unroll
+    for (int q = 0; q < r; ++q) w[q] = v[b + q * B];
+    if constexpr (Ns > 1) {
+      const int k = j & (Ns - 1);
+#pragma unroll
+      for (int q = 1; q < r; ++q) {
+        const cpx<T> c = tw[toff + (q - 1) * Ns + k];
+        w[q] = INV ? cmul_conj(w[q], c) : cmul(w[q], c);
+      }
+    }
+    dft<r, INV>(w);
+    if constexpr (last) {
+#pragma unroll
+      for (int q = 0; q < r; ++q) v[b + q * B] = w[q];
+    } else {
+      const int base = (j / Ns) * Ns * r + (j & (Ns - 1));
+#pragma unroll
+      for (int q = 0; q < r; ++q) lds[lds_idx(base + q * Ns)] = w[q];
+    }
+  }
+}
+
+template <int N, int S, bool INV, typename T>
+__device__ __forceinline__ void line_stages(cpx<T> (&v)[line_radix(N)], cpx<T>* lds, int t,
+                                            const cpx<T>* __restrict__ tw) {
+  constexpr int R = line_radix(N);
+  constexpr int TL = N / R;
+  if constexpr (S < num_stages(N, R)) {
+    line_stage<N, S, INV>(v, lds, t, tw);
+    if constexpr (S < num_stages(N, R) - 1) {
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < R; ++s) v[s] = lds[lds_idx(t + s * TL)];
+      __syncthreads();
+      line_stages<N, S + 1, INV>(v, lds, t, tw);
+    }
+  }
+}
+
+// Full unnormalised FFT of a line whose N/R owners all call this together
+// (every thread of the block must call it: it contains block barriers).
+template <int N, bool INV, typename T>
+__device__ __forceinline__ void line_fft(cpx<T> (&v)[line_radix(N)], cpx<T>* lds, int t,
+                                         const cpx<T>* __restrict__ tw) {
+  line_stages<N, 0, INV>(v, lds, t, tw);
+}
+
+}  // namespace pst

@@ -1,0 +1,133 @@
+// NLS split-step passes (Section "A Numerical Method for the Nonlinear
+// Schrodinger Equation").
+//
+// Between passes the field is held as H = FFT_x(psi): transformed along x
+// only.  Because the 2D transform factorises, one time step is two sweeps:
+//   row pass:    psi = iFFT_x(H);  psi *= exp(-i g |psi|^2 dt);  H = FFT_x(psi)
+//   column pass: psi_hat = FFT_y(H); psi_hat *= E_x[mx] E_y[my]; H = iFFT_y(psi_hat)
+// with E = exp(-i k^2 tau) separable in x and y.  Adjacent linear half steps
+// of consecutive Strang steps merge into one full step, so a call of n steps
+// is: entry row (FFT_x only), column (half), n-1 x [row, column (full)],
+// row, column (half), exit row (iFFT_x only).  The unnormalised transforms'
+// factors are folded into the phase coefficient and the E_y table.
+#include "kernels.hpp"
+#include "launch.hpp"
+
+namespace pst {
+
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_nls_row(
+    cpx<T>* psi, int nlines, T phase_coef, T scale, const cpx<T>* __restrict__ tw) {
+  using G = RowGeom<T, N>;
+  extern __shared__ char smem[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
+  const int lid = threadIdx.x / G::TL, t = threadIdx.x % G::TL;
+  const int line = blockIdx.x * G::LPB + lid;
+  const bool valid = line < nlines;
+  cpx<T>* L = lds + lid * lds_line_stride<T>(N);
+  cpx<T>* g = psi + (size_t)line * N;
+  cpx<T> v[G::R];
+#pragma unroll
+  for (int s = 0; s < G::R; ++s) v[s] = valid ? g[t + s * G::TL] : cpx<T>{0, 0};
+  if constexpr (MODE == 0) {
+    line_fft<N, false>(v, L, t, tw);
+#pragma unroll
+    for (int s = 0; s < G::R; ++s) v[s] = v[s] * scale;
+  } else if constexpr (MODE == 1) {
+    line_fft<N, true>(v, L, t, tw);
+#pragma unroll
+    for (int s = 0; s < G::R; ++s) v[s] = rotate_neg(v[s], phase_coef * norm2(v[s]));
+    line_fft<N, false>(v, L, t, tw);
+  } else {
+    line_fft<N, true>(v, L, t, tw);
+#pragma unroll
+    for (int s = 0; s < G::R; ++s) v[s] = v[s] * scale;
+  }
+  if (valid) {
+#pragma unroll
+    for (int s = 0; s < G::R; ++s) g[t + s * G::TL] = v[s];
+  }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(1024) void k_nls_col(cpx<T>* psi, int nx, int tiles_per_field,
+                                                  const cpx<T>* __restrict__ tw,
+                                                  const cpx<T>* __restrict__ ex,
+                                                  const cpx<T>* __restrict__ ey) {
+  using G = ColGeom<T, N>;
+  extern __shared__ char smem[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
+  const int W = blockDim.x / G::TL;
+  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int field = tile / tiles_per_field;
+  const int col = (tile % tiles_per_field) * W + c;
+  const bool valid = col < nx;
+  cpx<T>* base = psi + (size_t)field * N * nx + col;
+  cpx<T>* L = lds + c * lds_line_stride<T>(N);
+  cpx<T> v[G::R];
+#pragma unroll
+  for (int s = 0; s < G::R; ++s) v[s] = valid ? base[(size_t)(t + s * G::TL) * nx] : cpx<T>{0, 0};
+  line_fft<N, false>(v, L, t, tw);
+  const cpx<T> exc = valid ? ex[col] : cpx<T>{0, 0};
+#pragma unroll
+  for (int s = 0; s < G::R; ++s) v[s] = cmul(cmul(v[s], exc), ey[t + s * G::TL]);
+  line_fft<N, true>(v, L, t, tw);
+  if (valid) {
+#pragma unroll
+    for (int s = 0; s < G::R; ++s) base[(size_t)(t + s * G::TL) * nx] = v[s];
+  }
+}
+
+template <typename T>
+static hipError_t row(int nx, int nlines, void* psi, int mode, double pc, double scale,
+                      const void* tw, hipStream_t s) {
+  bool ok = dispatch_n(nx, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    using G = RowGeom<T, N>;
+    const int grid = (nlines + G::LPB - 1) / G::LPB;
+    if (mode == 0) {
+      allow_lds((k_nls_row<T, N, 0>), G::LDS_BYTES);
+      hipLaunchKernelGGL((k_nls_row<T, N, 0>), dim3(grid), dim3(G::THREADS), G::LDS_BYTES, s,
+                         (cpx<T>*)psi, nlines, (T)pc, (T)scale, (const cpx<T>*)tw);
+    } else if (mode == 1) {
+      allow_lds((k_nls_row<T, N, 1>), G::LDS_BYTES);
+      hipLaunchKernelGGL((k_nls_row<T, N, 1>), dim3(grid), dim3(G::THREADS), G::LDS_BYTES, s,
+                         (cpx<T>*)psi, nlines, (T)pc, (T)scale, (const cpx<T>*)tw);
+    } else {
+      allow_lds((k_nls_row<T, N, 2>), G::LDS_BYTES);
+      hipLaunchKernelGGL((k_nls_row<T, N, 2>), dim3(grid), dim3(G::THREADS), G::LDS_BYTES, s,
+                         (cpx<T>*)psi, nlines, (T)pc, (T)scale, (const cpx<T>*)tw);
+    }
+  });
+  return ok ? hipGetLastError() : hipErrorInvalidValue;
+}
+
+hipError_t nls_row(Prec p, int nx, int nlines, void* psi, int mode, double phase_coef, double scale,
+                   const void* tw, hipStream_t s) {
+  return p == P32 ? row<float>(nx, nlines, psi, mode, phase_coef, scale, tw, s)
+                  : row<double>(nx, nlines, psi, mode, phase_coef, scale, tw, s);
+}
+
+template <typename T>
+static hipError_t col(int ny, int nx, int nfields, void* psi, const void* tw, const void* ex,
+                      const void* ey, int W, hipStream_t s) {
+  bool ok = dispatch_n(ny, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    using G = ColGeom<T, N>;
+    const int tiles = (nx + W - 1) / W;
+    allow_lds((k_nls_col<T, N>), G::lds_bytes(W));
+    hipLaunchKernelGGL((k_nls_col<T, N>), dim3(tiles * nfields), dim3(W * G::TL), G::lds_bytes(W), s,
+                       (cpx<T>*)psi, nx, tiles, (const cpx<T>*)tw, (const cpx<T>*)ex,
+                       (const cpx<T>*)ey);
+  });
+  return ok ? hipGetLastError() : hipErrorInvalidValue;
+}
+
+hipError_t nls_col(Prec p, int ny, int nx, int nfields, void* psi, const void* tw, const void* ex,
+                   const void* ey, int W, hipStream_t s) {
+  return p == P32 ? col<float>(ny, nx, nfields, psi, tw, ex, ey, W, s)
+                  : col<double>(ny, nx, nfields, psi, tw, ex, ey, W, s);
+}
+
+}  // namespace pst

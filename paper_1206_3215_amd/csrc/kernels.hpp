@@ -1,0 +1,132 @@
+// Pass geometry and shared helpers of the pst kernels (gfx950).
+//
+// A "row pass" transforms lines along x (contiguous, length nx); a "column
+// pass" transforms lines along y (stride = row length, length ny).  Both
+// keep a line in registers (R values per thread, N/R threads per line) and
+// use LDS only for the exchanges between Stockham stages.
+#pragma once
+
+#include <type_traits>
+#include <utility>
+
+#include "fft_line.hpp"
+#include "launch.hpp"
+
+namespace pst {
+
+// LDS slots per line, including one pad slot per 16 elements and a tail
+// that shifts consecutive lines of a column tile by half of the LDS bank
+// space (128 bytes).
+template <typename T>
+__host__ __device__ constexpr int lds_line_stride(int N) {
+  return N + N / 16 + (int)(128 / sizeof(cpx<T>));
+}
+
+// Row pass: LPB lines per block, N/R threads per line, >= 256 threads per
+// block when the line is short.
+template <typename T, int N>
+struct RowGeom {
+  static constexpr int R = line_radix(N);
+  static constexpr int TL = N / R;
+  static constexpr int LPB = TL >= 256 ? 1 : 256 / TL;
+  static constexpr int THREADS = LPB * TL;
+  static constexpr size_t LDS_BYTES = (size_t)LPB * lds_line_stride<T>(N) * sizeof(cpx<T>);
+};
+
+// Column pass: W adjacent columns per block (W chosen at run time), thread
+// (c, t) with c fastest so that a wave reads W consecutive elements of a
+// row per instruction.
+template <typename T, int N>
+struct ColGeom {
+  static constexpr int R = line_radix(N);
+  static constexpr int TL = N / R;
+  static constexpr int MAX_THREADS = 1024;
+  static size_t lds_bytes(int W) { return (size_t)W * lds_line_stride<T>(N) * sizeof(cpx<T>); }
+};
+
+// Blocks are handed to the 8 XCDs of the chip round robin (block b runs on
+// XCD b mod 8).  Give each XCD a contiguous range of tiles, so that the
+// column tiles sharing a 128-byte line are read through the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
+  const int q = nblocks >> 3, rem = nblocks & 7;
+  const int x = b & 7, i = b >> 3;
+  return x * q + (x < rem ? x : rem) + i;
+}
+
+// v * exp(-i theta), written as v + v*(cos(theta) - 1 - i sin(theta)) with
+// cos(theta) - 1 = -2 sin^2(theta/2): for the small angles of a time step
+// the correction is tiny, so rounding does not bias |v| (a rounded
+// cos(theta) near 1 would).  Short Taylor series for |theta| <= 1/8, library
+// sincos otherwise.
+__device__ __forceinline__ cpx<float> rotate_neg(cpx<float> v, float th) {
+  float cm1, s;
+  if (fabsf(th) <= 0.125f) {
+    const float t2 = th * th;
+    cm1 = t2 * (-0.5f + t2 * (1.0f / 24 + t2 * (-1.0f / 720 + t2 * (1.0f / 40320))));
+    s = th * (1.0f + t2 * (-1.0f / 6 + t2 * (1.0f / 120 + t2 * (-1.0f / 5040))));
+  } else {
+    float sh, ch;
+    sincosf(0.5f * th, &sh, &ch);
+    cm1 = -2.0f * sh * sh;
+    s = 2.0f * sh * ch;
+  }
+  return cpx<float>{v.re + (v.re * cm1 + v.im * s), v.im + (v.im * cm1 - v.re * s)};
+}
+__device__ __forceinline__ cpx<double> rotate_neg(cpx<double> v, double th) {
+  double sh, ch;
+  sincos(0.5 * th, &sh, &ch);
+  const double cm1 = -2.0 * sh * sh, s = 2.0 * sh * ch;
+  return cpx<double>{v.re + (v.re * cm1 + v.im * s), v.im + (v.im * cm1 - v.re * s)};
+}
+
+// Deterministic sum of one double per thread over the n threads of a line
+// (n a power of two); the thread with index t of line `line` owns slot
+// line*n + t of red.  Tree order is fixed.  Every thread of the block must
+// call it with the same n.  The result is returned to every thread of the
+// line.
+__device__ __forceinline__ double line_sum(double* red, int line, int t, int n, double v) {
+  double* r = red + line * n;
+  r[t] = v;
+  __syncthreads();
+  for (int h = n >> 1; h > 0; h >>= 1) {
+    if (t < h) r[t] += r[t + h];
+    __syncthreads();
+  }
+  const double out = r[0];
+  __syncthreads();
+  return out;
+}
+
+// Kernels whose dynamic LDS exceeds 64 KiB must opt in once (gfx950 has
+// 160 KiB per workgroup).
+template <class K>
+inline void allow_lds(K kernel, size_t bytes) {
+  if (bytes > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// ---------------------------------------------------------- N dispatch ---
+template <int N>
+using IntC = std::integral_constant<int, N>;
+
+template <class F>
+bool dispatch_n(int n, F&& f) {
+  switch (n) {
+    case 4: f(IntC<4>{}); return true;
+    case 8: f(IntC<8>{}); return true;
+    case 16: f(IntC<16>{}); return true;
+    case 32: f(IntC<32>{}); return true;
+    case 64: f(IntC<64>{}); return true;
+    case 128: f(IntC<128>{}); return true;
+    case 256: f(IntC<256>{}); return true;
+    case 512: f(IntC<512>{}); return true;
+    case 1024: f(IntC<1024>{}); return true;
+    case 2048: f(IntC<2048>{}); return true;
+    case 4096: f(IntC<4096>{}); return true;
+    case 8192: f(IntC<8192>{}); return true;
+    default: return false;
+  }
+}
+
+}  // namespace pst

@@ -1,0 +1,70 @@
+// Internal definitions shared by the host-side translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <string>
+#include <vector>
+
+#include "launch.hpp"
+#include "pst.h"
+
+// Cached NLS propagator tables for one (dt, domain).
+struct NlsTables {
+  bool valid = false;
+  double dt = 0, lx = 0, ly = 0;
+  void* ex_half = nullptr;  // exp(-i kx^2 dt/2)
+  void* ex_full = nullptr;  // exp(-i kx^2 dt)
+  void* ey_half = nullptr;  // exp(-i ky^2 dt/2) / (nx ny)
+  void* ey_full = nullptr;  // exp(-i ky^2 dt) / (nx ny)
+};
+
+struct pst_plan_s {
+  int nx = 0, ny = 0, batch = 1;
+  pst_kind kind = PST_C2C;
+  pst_prec prec = PST_FP32;
+  pst::Prec P = pst::P32;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  size_t csize = 8, rsize = 4;  // bytes per complex / real element
+  int Wcol = 1;                 // column tile (columns per block) for length ny
+  void* tw_x = nullptr;         // twiddles of the x lines (length nx)
+  void* tw_y = nullptr;         // twiddles of the y lines (length ny)
+  int* dstatus = nullptr;       // latched device status bits
+  double* dres = nullptr;       // batch*8 doubles of reduction results
+  std::vector<void*> owned;     // device allocations released with the plan
+  // workspace
+  void* ws = nullptr;
+  bool ws_owned = false;
+  size_t ws_need = 0;
+  size_t off_spec = 0, off_spec2 = 0, off_spec3 = 0, off_hyb = 0, off_rowpart = 0, off_colpart = 0;
+  NlsTables nls;
+  // per-pass timing (pst_profile_enable)
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_rec;
+};
+
+namespace pst {
+
+typedef pst_plan_s Plan;
+
+pst_status fail(pst_status st, const char* fmt, ...);
+pst_status hip_check(hipError_t e, const char* what);
+pst_status upload_complex(Plan* pl, const std::vector<std::complex<double>>& h, void** dptr, bool unit,
+                          double scale);
+pst_status check_domain(const pst_domain& d);
+pst_status check_field(const void* p, const char* name);
+pst_status ensure_workspace(Plan* pl);
+double wavenumber(int m, int n, double length);
+
+// Bracket one pass launch with events when profiling is on.
+void prof_begin(Plan* pl, int pass);
+void prof_end(Plan* pl);
+
+inline void* ws_at(Plan* pl, size_t off) { return static_cast<char*>(pl->ws) + off; }
+inline int col_w(Plan* pl, int n) { return n == pl->ny ? pl->Wcol : col_tile_max(pl->P, n); }
+
+}  // namespace pst

@@ -1,0 +1,64 @@
+"""2D FFT through the C ABI vs the oracle's FP64 transform."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import spectral as sp
+from tests.gpuutil import need_gpu, rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(4, 4, 1), (8, 16, 2), (16, 8, 1), (32, 64, 3), (64, 64, 1), (128, 32, 2), (256, 512, 1),
+          (1024, 1024, 1), (2048, 64, 1), (64, 4096, 1), (4096, 4096, 1), (8192, 16, 1)]
+TOL = {0: 1e-5, 1: 1e-13}
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("nx,ny,batch", SHAPES)
+def test_c2c_forward_inverse(nx, ny, batch, prec):
+    torch = need_gpu()
+    from paper_1206_3215_amd import binding as b
+    rng = np.random.default_rng(nx * 7 + ny + batch)
+    x = rng.standard_normal((batch, ny, nx)) + 1j * rng.standard_normal((batch, ny, nx))
+    plan = b.Plan(nx, ny, b.PST_C2C, prec, batch)
+    xd = to_dev(x, torch, plan.complex_dtype)
+    yd = torch.empty_like(xd)
+    plan.fft2d_exec(xd, yd, -1)
+    ref = np.stack([sp.fft2(x[i]) for i in range(batch)])
+    assert rel_err(to_host(yd), ref) < TOL[prec] * math.log2(nx * ny)
+    plan.fft2d_exec(yd, yd, +1)                     # in place inverse
+    assert rel_err(to_host(yd), x) < TOL[prec] * math.log2(nx * ny)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("nx,ny,batch", [(4, 4, 1), (8, 8, 3), (16, 64, 1), (64, 32, 2), (256, 256, 1),
+                                         (1024, 512, 1), (2048, 2048, 1), (4096, 128, 1)])
+def test_r2c_c2r(nx, ny, batch, prec):
+    torch = need_gpu()
+    from paper_1206_3215_amd import binding as b
+    rng = np.random.default_rng(nx + 3 * ny + batch)
+    x = rng.standard_normal((batch, ny, nx))
+    plan = b.Plan(nx, ny, b.PST_R2C, prec, batch)
+    xd = to_dev(x, torch, plan.real_dtype)
+    yd = torch.empty((batch, ny, nx // 2 + 1), dtype=plan.complex_dtype, device="cuda")
+    plan.fft2d_exec(xd, yd, -1)
+    ref = np.stack([sp.rfft2(x[i]) for i in range(batch)])
+    assert rel_err(to_host(yd), ref) < TOL[prec] * math.log2(nx * ny)
+    zd = torch.empty_like(xd)
+    plan.fft2d_exec(yd, zd, +1)
+    assert rel_err(to_host(zd), x) < TOL[prec] * math.log2(nx * ny)
+    assert to_host(yd).shape == (batch, ny, nx // 2 + 1)
+
+
+def test_c2r_ignores_imaginary_dc_and_nyquist():
+    # numpy's inverse real transform drops Im of the self-conjugate modes.
+    torch = need_gpu()
+    from paper_1206_3215_amd import binding as b
+    nx = ny = 16
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal((1, ny, nx // 2 + 1)) + 1j * rng.standard_normal((1, ny, nx // 2 + 1))
+    plan = b.Plan(nx, ny, b.PST_R2C, 1, 1)
+    out = torch.empty((1, ny, nx), dtype=torch.float64, device="cuda")
+    plan.fft2d_exec(to_dev(X, torch, torch.complex128), out, +1)
+    assert rel_err(to_host(out)[0], sp.irfft2(X[0], (ny, nx))) < 1e-13

@@ -1,0 +1,120 @@
+"""NLS split-step through the C ABI vs the FP64 oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import nls as onls
+from paper_1206_3215_amd import inputs
+from tests.gpuutil import need_gpu, rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+# Stated tolerances: max relative error vs the FP64 oracle.
+TOL = {0: 1e-4, 1: 1e-11}
+
+
+def run_gpu(psi0, d, dt, g, nsteps, prec, chunk=None, diag=False):
+    torch = need_gpu()
+    from paper_1206_3215_amd import binding as b
+    batch = psi0.shape[0] if psi0.ndim == 3 else 1
+    ny, nx = psi0.shape[-2:]
+    plan = b.Plan(nx, ny, b.PST_C2C, prec, batch)
+    psi = to_dev(psi0.reshape(batch, ny, nx), torch, plan.complex_dtype)
+    diags = []
+    chunk = chunk or nsteps
+    done = 0
+    if diag:
+        diags.append(plan.conserved_quantities("nls", psi, d=d, dt=dt, g=g))
+    while done < nsteps:
+        k = min(chunk, nsteps - done)
+        plan.nls_step(psi, d, dt, g, k)
+        done += k
+        if diag:
+            diags.append(plan.conserved_quantities("nls", psi, d=d, dt=dt, g=g))
+    torch.cuda.synchronize()
+    return to_host(psi).reshape(psi0.shape), diags
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_small_workload_matches_oracle(prec):
+    # 64^2 on [-8pi,8pi)^2, seeded noise, dt 0.0025, 200 steps, diagnostics every 20.
+    d = inputs.NLS_SMALL_DOMAIN
+    psi0 = inputs.nls_gaussian(64, 64, d, seed=0)
+    ref, rdiag = onls.run(psi0, d.lx, d.ly, 0.0025, 1.0, 200, diag_every=20)
+    got, gdiag = run_gpu(psi0, d, 0.0025, 1.0, 200, prec, chunk=20, diag=True)
+    assert rel_err(got, ref) < TOL[prec]
+    gm = np.array([x[0, 0] for x in gdiag])
+    ge = np.array([x[0, 1] for x in gdiag])
+    rm = np.array([x[1] for x in rdiag])
+    re_ = np.array([x[2] for x in rdiag])
+    tol_q = 1e-12 if prec == 1 else 1e-5
+    assert np.max(np.abs(gm / rm - 1)) < tol_q
+    assert np.max(np.abs(ge / re_ - 1)) < tol_q
+    if prec == 1:
+        assert np.max(np.abs(gm / gm[0] - 1)) < 1e-12   # mass to rounding (paper's Results)
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("nx,ny,batch", [(16, 8, 1), (32, 32, 3), (128, 64, 2), (4, 4, 1)])
+def test_ragged_shapes_and_batches(nx, ny, batch, prec):
+    d = inputs.Domain(7.0, 5.0, -3.5, -2.5)
+    psi0 = np.stack([inputs.nls_gaussian(nx, ny, d, seed=s) for s in range(batch)]) * 1.7
+    got, _ = run_gpu(psi0, d, 0.01, -1.0, 7, prec)
+    for i in range(batch):
+        ref, _ = onls.run(psi0[i], d.lx, d.ly, 0.01, -1.0, 7)
+        assert rel_err(got[i], ref) < TOL[prec]
+
+
+def test_zero_and_one_step():
+    d = inputs.PAPER_DOMAIN
+    psi0 = inputs.nls_gaussian(64, 64, d, seed=1)
+    got0, _ = run_gpu(psi0, d, 1e-3, 1.0, 0, 1)
+    assert np.array_equal(got0, psi0)
+    got1, _ = run_gpu(psi0, d, 1e-3, 1.0, 1, 1)
+    ref1, _ = onls.run(psi0, d.lx, d.ly, 1e-3, 1.0, 1)
+    assert rel_err(got1, ref1) < 1e-12
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_plane_wave_closed_form_full_size(prec):
+    # Property at the headline size 4096^2 (any size): a plane wave is
+    # reproduced exactly by the split step for any dt.
+    n, L, A, dt, steps = 4096, 10 * math.pi, 0.3, 1e-3, 100
+    X, Y = inputs.grid(n, n, inputs.Domain(L, L, 0, 0))
+    k = 2 * math.pi * np.array([5, -3]) / L
+    psi0 = A * np.exp(1j * (k[0] * X + k[1] * Y))
+    got, _ = run_gpu(psi0, inputs.Domain(L, L, 0, 0), dt, 1.0, steps, prec)
+    exact = psi0 * np.exp(-1j * (k @ k + A * A) * dt * steps)
+    assert rel_err(got, exact) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_headline_size_against_oracle_short(prec):
+    # 4096^2 on [-5pi,5pi)^2, the benchmark's launch configuration, 10 steps.
+    d = inputs.PAPER_DOMAIN
+    psi0 = inputs.nls_gaussian(4096, 4096, d, seed=0)
+    ref, _ = onls.run(psi0, d.lx, d.ly, 1e-3, 1.0, 10)
+    got, _ = run_gpu(psi0, d, 1e-3, 1.0, 10, prec)
+    assert rel_err(got, ref) < TOL[prec]
+
+
+@pytest.fixture(scope="module")
+def oracle_1024_1000():
+    d = inputs.PAPER_DOMAIN
+    psi0 = inputs.nls_gaussian(1024, 1024, d, seed=0)
+    ref, diags = onls.run(psi0, d.lx, d.ly, 1e-3, 1.0, 1000, diag_every=1000)
+    return psi0, ref, diags
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_1024_thousand_steps_against_oracle(prec, oracle_1024_1000):
+    # Headline configuration at its 1024^2 grid: [-5pi,5pi)^2, dt 1e-3, 1000 steps.
+    d = inputs.PAPER_DOMAIN
+    psi0, ref, rdiag = oracle_1024_1000
+    got, gdiag = run_gpu(psi0, d, 1e-3, 1.0, 1000, prec, diag=True)
+    err = rel_err(got, ref)
+    print(f"prec={prec} rel_err={err:.3e} mass drift={gdiag[-1][0,0]/gdiag[0][0,0]-1:.3e}")
+    assert err < TOL[prec]
+    assert abs(gdiag[-1][0, 0] / rdiag[-1][1] - 1) < (1e-12 if prec else 1e-5)
