@@ -9,7 +9,11 @@
 // of consecutive Strang steps merge into one full step, so a call of n steps
 // is: entry row (FFT_x only), column (half), n-1 x [row, column (full)],
 // row, column (half), exit row (iFFT_x only).  The unnormalised transforms'
-// factors are folded into the phase coefficient and the E_y table.
+// factors go into the phase coefficient and one scaling in the column pass.
+// The propagator tables hold E - 1 = (cos - 1, -sin): multiplying as
+// v + v (E - 1) keeps |E| = 1 to within rounding of the small correction;
+// rounded (cos, -sin) pairs carry a bias of |E| near 1 for the energetic
+// low modes that would drain or feed the mass at every step.
 #include "kernels.hpp"
 #include "launch.hpp"
 
@@ -53,7 +57,7 @@ template <typename T, int N>
 __global__ __launch_bounds__(1024) void k_nls_col(cpx<T>* psi, int nx, int tiles_per_field,
                                                   const cpx<T>* __restrict__ tw,
                                                   const cpx<T>* __restrict__ ex,
-                                                  const cpx<T>* __restrict__ ey) {
+                                                  const cpx<T>* __restrict__ ey, T scale) {
   using G = ColGeom<T, N>;
   extern __shared__ char smem[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
@@ -69,9 +73,13 @@ __global__ __launch_bounds__(1024) void k_nls_col(cpx<T>* psi, int nx, int tiles
 #pragma unroll
   for (int s = 0; s < G::R; ++s) v[s] = valid ? base[(size_t)(t + s * G::TL) * nx] : cpx<T>{0, 0};
   line_fft<N, false>(v, L, t, tw);
-  const cpx<T> exc = valid ? ex[col] : cpx<T>{0, 0};
+  const cpx<T> exm = valid ? ex[col] : cpx<T>{0, 0};
 #pragma unroll
-  for (int s = 0; s < G::R; ++s) v[s] = cmul(cmul(v[s], exc), ey[t + s * G::TL]);
+  for (int s = 0; s < G::R; ++s) {
+    const cpx<T> w = v[s] * scale;
+    const cpx<T> wx = w + cmul(w, exm);
+    v[s] = wx + cmul(wx, ey[t + s * G::TL]);
+  }
   line_fft<N, true>(v, L, t, tw);
   if (valid) {
 #pragma unroll
@@ -119,7 +127,7 @@ static hipError_t col(int ny, int nx, int nfields, void* psi, const void* tw, co
     allow_lds((k_nls_col<T, N>), G::lds_bytes(W));
     hipLaunchKernelGGL((k_nls_col<T, N>), dim3(tiles * nfields), dim3(W * G::TL), G::lds_bytes(W), s,
                        (cpx<T>*)psi, nx, tiles, (const cpx<T>*)tw, (const cpx<T>*)ex,
-                       (const cpx<T>*)ey);
+                       (const cpx<T>*)ey, (T)(1.0 / ((double)nx * N)));
   });
   return ok ? hipGetLastError() : hipErrorInvalidValue;
 }

@@ -1,0 +1,393 @@
+// Navier-Stokes passes: Crank-Nicolson in time with fixed-point iteration on
+// the Jacobian (Section "A Numerical Method for the 2D Navier-Stokes
+// Equation"), vorticity/stream function form, 2/3-rule dealiasing.
+//
+// With h = dt nu |k|^2 / 2 and N = FFT(J), J = psi_y omega_x - psi_x omega_y,
+// the iterate of step n solves per mode
+//     w^{k+1} = [(1 - h) w^n - dt/2 (N(w^n) + N(w^k))] / (1 + h).
+// It is carried as the increment d = w - w^n:
+//     q = -2 h w^n - dt/2 N(w^n)              (once per step)
+//     d^{k+1} = (q - dt/2 N(w^k)) / (1 + h)
+// so that single-precision coefficients near 1 never multiply the whole
+// field; the fixed-point residual is then |d^{k+1} - d^k|^2 (Parseval).
+//
+// Spectral arrays are [field][ny][nx/2+1] complex; "hybrid" arrays hold the
+// same layout transformed along x only.  Per iteration:
+//   row pass (row pairs): 4 derivative hybrids -> C2R_x in pairs
+//       (psi_y, psi_x), (omega_x, omega_y) -> J = psi_y omega_x - psi_x omega_y
+//       -> R2C_x of the two rows' J -> N hybrid (times 2)
+//   column pass: FFT_y(N hybrid) -> mask -> update d, residual ->
+//       derivatives i ky psi, i kx w, i kx psi, i ky w of w = w^n + d ->
+//       4 x iFFT_y -> derivative hybrids (scaled for the next C2R_x)
+#include "kernels.hpp"
+#include "launch.hpp"
+
+namespace pst {
+
+enum { NS_ENTRY = 0, NS_FIRST = 1, NS_ITER = 2, NS_EXIT = 3 };
+
+// A block's lines may span several fields; it may skip its work only when
+// every field it touches has converged (the decision must be block-uniform).
+__device__ __forceinline__ bool fields_done(const int* done, int f0, int f1) {
+  for (int f = f0; f <= f1; ++f)
+    if (!done[f]) return false;
+  return true;
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_ns_row(
+    const cpx<T>* D, size_t dstride, cpx<T>* NH, int nlines, int ny, const int* done,
+    const cpx<T>* __restrict__ tw) {
+  using G = RowGeom<T, N>;
+  constexpr int H = N / 2 + 1;
+  extern __shared__ char smem[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
+  const int lid = threadIdx.x / G::TL, t = threadIdx.x % G::TL;
+  const int pair = blockIdx.x * G::LPB + lid;
+  const int la = 2 * pair, lb = 2 * pair + 1;
+  const bool va = la < nlines, vb = lb < nlines;
+  if (done != nullptr) {
+    const int p0 = blockIdx.x * G::LPB;
+    const int l1 = min(2 * (p0 + G::LPB) - 1, nlines - 1);
+    if (fields_done(done, (2 * p0) / ny, l1 / ny)) return;
+  }
+  cpx<T>* L = lds + lid * lds_line_stride<T>(N);
+  const size_t oa = (size_t)la * H, ob = (size_t)lb * H;
+  // Fields of like magnitude share a complex transform: cp = psi_y + i psi_x
+  // and cw = omega_x + i omega_y (packing psi with omega, whose sizes differ
+  // by ~|k|^2, would bury the stream-function derivatives in the vorticity
+  // derivatives' rounding).  Then J = Re(cp * cw).
+  T ja[G::R];
+  cpx<T> cp[G::R], c[G::R];
+  load_pair_spectrum<T, N>(cp, D + oa, D + 2 * dstride + oa, t, va, va, T(1));
+  line_fft<N, true>(cp, L, t, tw);
+  load_pair_spectrum<T, N>(c, D + dstride + oa, D + 3 * dstride + oa, t, va, va, T(1));
+  line_fft<N, true>(c, L, t, tw);
+#pragma unroll
+  for (int s = 0; s < G::R; ++s) ja[s] = cp[s].re * c[s].re - cp[s].im * c[s].im;
+  load_pair_spectrum<T, N>(cp, D + ob, D + 2 * dstride + ob, t, vb, vb, T(1));
+  line_fft<N, true>(cp, L, t, tw);
+  load_pair_spectrum<T, N>(c, D + dstride + ob, D + 3 * dstride + ob, t, vb, vb, T(1));
+  line_fft<N, true>(c, L, t, tw);
+#pragma unroll
+  for (int s = 0; s < G::R; ++s) c[s] = cpx<T>{ja[s], cp[s].re * c[s].re - cp[s].im * c[s].im};
+  line_fft<N, false>(c, L, t, tw);
+  store_pair_halves<T, N>(c, L, t, NH + oa, NH + ob, va, vb);
+}
+
+struct NsColArgs {
+  double kx0, ky0;  // 2 pi / lx, 2 pi / ly
+  double hnu;       // dt nu / 2
+  double qdt;       // dt / 2
+  double nscale;    // 1/2: the row pass stores 2 x the Jacobian's transform
+  double dscale;    // 1 / (nx ny): scale of the derivative hybrids
+  int nx, kx_cut, ky_cut;
+};
+
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__(1024) void k_ns_col(const cpx<T>* NH, cpx<T>* WN, cpx<T>* Q, cpx<T>* DK,
+                                                 cpx<T>* D, size_t dstride, cpx<T>* OUT, double* part,
+                                                 int tiles_per_field, const int* done, NsColArgs a,
+                                                 const cpx<T>* __restrict__ tw) {
+  using G = ColGeom<T, N>;
+  constexpr int MY = N;  // column length (ny)
+  extern __shared__ char smem[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
+  __shared__ double red[1024];
+  const int ncols = a.nx / 2 + 1;
+  const int Wt = blockDim.x / G::TL;
+  const int c = threadIdx.x % Wt, t = threadIdx.x / Wt;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int field = tile / tiles_per_field;
+  if (MODE == NS_ITER && done[field]) return;  // uniform: a block is one field
+  const int col = (tile % tiles_per_field) * Wt + c;
+  const bool valid = col < ncols;
+  const size_t off = (size_t)field * MY * ncols + col;
+  cpx<T>* L = lds + c * lds_line_stride<T>(MY);
+  auto at = [&](int s) { return off + (size_t)(t + s * G::TL) * ncols; };
+  cpx<T> w[G::R], v[G::R];
+
+  if constexpr (MODE == NS_EXIT) {
+#pragma unroll
+    for (int s = 0; s < G::R; ++s) v[s] = valid ? WN[at(s)] + DK[at(s)] : cpx<T>{0, 0};
+    line_fft<MY, true>(v, L, t, tw);
+    if (valid) {
+#pragma unroll
+      for (int s = 0; s < G::R; ++s) OUT[at(s)] = v[s];
+    }
+    return;
+  } else {
+    const T kx = (T)(a.kx0 * col);
+    const T kxd = (col == a.nx / 2) ? T(0) : kx;  // Nyquist dropped for first derivatives
+    const bool xkeep = col <= a.kx_cut;
+    double res = 0.0, ens = 0.0;
+    // N hybrid -> spectrum (entry: omega's x-transform -> w^n)
+#pragma unroll
+    for (int s = 0; s < G::R; ++s) v[s] = valid ? NH[at(s)] : cpx<T>{0, 0};
+    line_fft<MY, false>(v, L, t, tw);
+    if constexpr (MODE == NS_ENTRY) {
+#pragma unroll
+      for (int s = 0; s < G::R; ++s) {
+        w[s] = v[s];
+        if (valid) {
+          WN[at(s)] = v[s];
+          DK[at(s)] = cpx<T>{0, 0};
+        }
+      }
+    } else {
+      const T hnu = (T)a.hnu, qdt = (T)a.qdt;
+#pragma unroll
+      for (int s = 0; s < G::R; ++s) {
+        const int e = t + s * G::TL;
+        const int my = e < MY / 2 ? e : e - MY;
+        const T ky = (T)(a.ky0 * my);
+        const T h = hnu * (kx * kx + ky * ky);
+        const bool keep = xkeep && (my <= a.ky_cut && -my <= a.ky_cut);
+        const cpx<T> nk = keep ? v[s] * (T)a.nscale : cpx<T>{0, 0};
+        cpx<T> wn, q, dold;
+        if (MODE == NS_FIRST) {
+          // w^n = WN + (last step's increment); q = -2 h w^n - dt/2 N(w^n)
+          wn = valid ? WN[at(s)] + DK[at(s)] : cpx<T>{0, 0};
+          q = cpx<T>{T(-2) * h * wn.re - qdt * nk.re, T(-2) * h * wn.im - qdt * nk.im};
+          dold = cpx<T>{0, 0};
+          if (valid) {
+            WN[at(s)] = wn;
+            Q[at(s)] = q;
+          }
+        } else {
+          wn = valid ? WN[at(s)] : cpx<T>{0, 0};
+          q = valid ? Q[at(s)] : cpx<T>{0, 0};
+          dold = valid ? DK[at(s)] : cpx<T>{0, 0};
+        }
+        const T inv = T(1) / (T(1) + h);
+        const cpx<T> dnew = cpx<T>{(q.re - qdt * nk.re) * inv, (q.im - qdt * nk.im) * inv};
+        if (valid) DK[at(s)] = dnew;
+        const double dr = (double)dnew.re - (double)dold.re, di = (double)dnew.im - (double)dold.im;
+        res += dr * dr + di * di;
+        w[s] = wn + dnew;
+        ens += (double)w[s].re * w[s].re + (double)w[s].im * w[s].im;
+      }
+    }
+    // residual and |w|^2 partials, weighted for the half spectrum
+    if (MODE != NS_ENTRY) {
+      const double wt = (col == 0 || col == a.nx / 2) ? 1.0 : 2.0;
+      res = line_sum(red, c, t, G::TL, res * wt);
+      ens = line_sum(red, c, t, G::TL, ens * wt);
+      if (valid && t == 0) {
+        part[2 * ((size_t)field * ncols + col)] = res;
+        part[2 * ((size_t)field * ncols + col) + 1] = ens;
+      }
+    }
+    // derivative hybrids of w: psi_y, omega_x, psi_x, omega_y
+    const T dsc = (T)a.dscale;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+      for (int s = 0; s < G::R; ++s) {
+        const int e = t + s * G::TL;
+        const int my = e < MY / 2 ? e : e - MY;
+        const T ky = (T)(a.ky0 * my);
+        const T kyd = (e == MY / 2) ? T(0) : ky;
+        const T k2 = kx * kx + ky * ky;
+        const T ik2 = k2 > T(0) ? dsc / k2 : T(0);  // psi_hat = w / |k|^2, psi_hat(0) = 0
+        const T f = q == 0 ? kyd * ik2 : q == 1 ? kxd * dsc : q == 2 ? kxd * ik2 : kyd * dsc;
+        v[s] = mul_i(w[s]) * f;
+      }
+      line_fft<MY, true>(v, L, t, tw);
+      if (valid) {
+#pragma unroll
+        for (int s = 0; s < G::R; ++s) D[q * dstride + at(s)] = v[s];
+      }
+    }
+  }
+}
+
+// Per field: residual r = dxdy/(nx ny) sum w |d^{k+1} - d^k|^2 against
+// tol_eff = max(tol, fp_floor * integral omega^2); updates done/iters.
+// mode 0: first iteration of a step; 1: later iterations; fixed > 0: run
+// exactly that many iterations.
+__global__ __launch_bounds__(256) void k_ns_finish(int ncols, const double* part, double vol, double tol,
+                                                   double fp_floor, int max_iter, int fixed, int first,
+                                                   int* done, int* iters, int* iters_out, double* resid,
+                                                   int* status) {
+  __shared__ double red[256];
+  const int f = blockIdx.x, t = threadIdx.x;
+  if (!first && done[f]) return;
+  double r = 0.0, z = 0.0;
+  for (int i = t; i < ncols; i += 256) {
+    r += part[2 * ((size_t)f * ncols + i)];
+    z += part[2 * ((size_t)f * ncols + i) + 1];
+  }
+  r = line_sum(red, 0, t, 256, r);
+  z = line_sum(red, 0, t, 256, z);
+  if (t == 0) {
+    const int it = first ? 1 : iters[f] + 1;
+    iters[f] = it;
+    const double res = vol * r, tol_eff = fmax(tol, fp_floor * vol * z);
+    if (resid) resid[f] = res;
+    bool fin;
+    if (fixed > 0) {
+      fin = it >= fixed;
+    } else {
+      fin = res < tol_eff;
+      if (!fin && it >= max_iter) {
+        fin = true;
+        atomicOr(status, (int)ST_NOT_CONVERGED);
+      }
+    }
+    if (!isfinite(res)) {
+      fin = true;
+      atomicOr(status, (int)ST_NONFINITE);
+    }
+    done[f] = fin ? 1 : 0;
+    if (iters_out) iters_out[f] = it;
+  }
+}
+
+// Diagnostics: energy (1/2) sum_{k != 0} |w|^2/|k|^2 and enstrophy
+// (1/2) sum |w|^2 over the full spectrum (half-spectrum weights).
+template <typename T, int N>
+__global__ __launch_bounds__(1024) void k_ns_cq_col(const cpx<T>* XH, double* part, int nx, int tiles_per_field,
+                                                    double kx0, double ky0, const cpx<T>* __restrict__ tw) {
+  using G = ColGeom<T, N>;
+  extern __shared__ char smem[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
+  __shared__ double red[1024];
+  const int ncols = nx / 2 + 1;
+  const int Wt = blockDim.x / G::TL;
+  const int c = threadIdx.x % Wt, t = threadIdx.x / Wt;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int field = tile / tiles_per_field;
+  const int col = (tile % tiles_per_field) * Wt + c;
+  const bool valid = col < ncols;
+  const size_t off = (size_t)field * N * ncols + col;
+  cpx<T>* L = lds + c * lds_line_stride<T>(N);
+  cpx<T> v[G::R];
+#pragma unroll
+  for (int s = 0; s < G::R; ++s) v[s] = valid ? XH[off + (size_t)(t + s * G::TL) * ncols] : cpx<T>{0, 0};
+  line_fft<N, false>(v, L, t, tw);
+  const double kx = kx0 * col;
+  double en = 0.0, zz = 0.0;
+#pragma unroll
+  for (int s = 0; s < G::R; ++s) {
+    const int e = t + s * G::TL;
+    const double ky = ky0 * (e < N / 2 ? e : e - N);
+    const double k2 = kx * kx + ky * ky;
+    const double a2 = (double)v[s].re * v[s].re + (double)v[s].im * v[s].im;
+    zz += a2;
+    if (k2 > 0.0) en += a2 / k2;
+  }
+  const double wt = (col == 0 || col == nx / 2) ? 1.0 : 2.0;
+  en = line_sum(red, c, t, G::TL, en * wt);
+  zz = line_sum(red, c, t, G::TL, zz * wt);
+  if (valid && t == 0) {
+    part[2 * ((size_t)field * ncols + col)] = en;
+    part[2 * ((size_t)field * ncols + col) + 1] = zz;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ns_cq_finish(int ncols, const double* part, double en_coef, double zz_coef,
+                                                      double* out, int* status) {
+  __shared__ double red[256];
+  const int f = blockIdx.x, t = threadIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int i = t; i < ncols; i += 256) {
+    a += part[2 * ((size_t)f * ncols + i)];
+    b += part[2 * ((size_t)f * ncols + i) + 1];
+  }
+  a = line_sum(red, 0, t, 256, a);
+  b = line_sum(red, 0, t, 256, b);
+  if (t == 0) {
+    out[4 * f + 0] = en_coef * a;
+    out[4 * f + 1] = zz_coef * b;
+    out[4 * f + 2] = 0.0;
+    out[4 * f + 3] = 0.0;
+    if (!isfinite(a) || !isfinite(b)) atomicOr(status, (int)ST_NONFINITE);
+  }
+}
+
+// ----------------------------------------------------------- launchers ---
+template <typename T>
+static hipError_t row(int nx, int nlines, int ny, const void* D, size_t dstride, void* NH, const int* done,
+                      const void* tw, hipStream_t s) {
+  bool ok = dispatch_n(nx, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    using G = RowGeom<T, N>;
+    const int grid = ((nlines + 1) / 2 + G::LPB - 1) / G::LPB;
+    allow_lds(k_ns_row<T, N>, G::LDS_BYTES);
+    hipLaunchKernelGGL((k_ns_row<T, N>), dim3(grid), dim3(G::THREADS), G::LDS_BYTES, s, (const cpx<T>*)D, dstride,
+                       (cpx<T>*)NH, nlines, ny, done, (const cpx<T>*)tw);
+  });
+  return ok ? hipGetLastError() : hipErrorInvalidValue;
+}
+
+hipError_t ns_row(Prec p, int nx, int nlines, int ny, const void* D, size_t dstride, void* NH, const int* done,
+                  const void* tw, hipStream_t s) {
+  return p == P32 ? row<float>(nx, nlines, ny, D, dstride, NH, done, tw, s)
+                  : row<double>(nx, nlines, ny, D, dstride, NH, done, tw, s);
+}
+
+template <typename T>
+static hipError_t col(int mode, int ny, int nfields, const NsPtrs& P, const NsScalars& S, const int* done,
+                      const void* tw, int Wt, hipStream_t s) {
+  bool ok = dispatch_n(ny, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    using G = ColGeom<T, N>;
+    const int ncols = S.nx / 2 + 1;
+    const int tiles = (ncols + Wt - 1) / Wt;
+    NsColArgs a{S.kx0, S.ky0, S.hnu, S.qdt, S.nscale, S.dscale, S.nx, S.kx_cut, S.ky_cut};
+    auto go = [&](auto kern) {
+      allow_lds(kern, G::lds_bytes(Wt));
+      hipLaunchKernelGGL(kern, dim3(tiles * nfields), dim3(Wt * G::TL), G::lds_bytes(Wt), s, (const cpx<T>*)P.NH,
+                         (cpx<T>*)P.WN, (cpx<T>*)P.Q, (cpx<T>*)P.DK, (cpx<T>*)P.D, P.dstride, (cpx<T>*)P.OUT,
+                         P.part, tiles, done, a, (const cpx<T>*)tw);
+    };
+    if (mode == NS_ENTRY) go(k_ns_col<T, N, NS_ENTRY>);
+    else if (mode == NS_FIRST) go(k_ns_col<T, N, NS_FIRST>);
+    else if (mode == NS_ITER) go(k_ns_col<T, N, NS_ITER>);
+    else go(k_ns_col<T, N, NS_EXIT>);
+  });
+  return ok ? hipGetLastError() : hipErrorInvalidValue;
+}
+
+hipError_t ns_col(Prec p, int mode, int ny, int nfields, const NsPtrs& P, const NsScalars& S, const int* done,
+                  const void* tw, int Wt, hipStream_t s) {
+  return p == P32 ? col<float>(mode, ny, nfields, P, S, done, tw, Wt, s)
+                  : col<double>(mode, ny, nfields, P, S, done, tw, Wt, s);
+}
+
+hipError_t ns_finish(int nfields, int ncols, const double* part, double vol, double tol, double fp_floor,
+                     int max_iter, int fixed, int first, int* done, int* iters, int* iters_out, double* resid,
+                     int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_ns_finish, dim3(nfields), dim3(256), 0, s, ncols, part, vol, tol, fp_floor, max_iter, fixed,
+                     first, done, iters, iters_out, resid, status);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t cqcol(int ny, int nx, int nfields, const void* XH, double* part, double kx0, double ky0,
+                        const void* tw, int Wt, hipStream_t s) {
+  bool ok = dispatch_n(ny, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    using G = ColGeom<T, N>;
+    const int tiles = (nx / 2 + 1 + Wt - 1) / Wt;
+    allow_lds(k_ns_cq_col<T, N>, G::lds_bytes(Wt));
+    hipLaunchKernelGGL((k_ns_cq_col<T, N>), dim3(tiles * nfields), dim3(Wt * G::TL), G::lds_bytes(Wt), s,
+                       (const cpx<T>*)XH, part, nx, tiles, kx0, ky0, (const cpx<T>*)tw);
+  });
+  return ok ? hipGetLastError() : hipErrorInvalidValue;
+}
+
+hipError_t ns_cq_col(Prec p, int ny, int nx, int nfields, const void* XH, double* part, double kx0, double ky0,
+                     const void* tw, int Wt, hipStream_t s) {
+  return p == P32 ? cqcol<float>(ny, nx, nfields, XH, part, kx0, ky0, tw, Wt, s)
+                  : cqcol<double>(ny, nx, nfields, XH, part, kx0, ky0, tw, Wt, s);
+}
+
+hipError_t ns_cq_finish(int nfields, int ncols, const double* part, double en_coef, double zz_coef, double* out,
+                        int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_ns_cq_finish, dim3(nfields), dim3(256), 0, s, ncols, part, en_coef, zz_coef, out, status);
+  return hipGetLastError();
+}
+
+}  // namespace pst

@@ -1,0 +1,332 @@
+// Sine-Gordon passes: the three-level scheme of Section "A Numerical Method
+// for the Sine-Gordon Equation" (Laplacian sign as in eq. sg).  In Fourier
+// space, with a = |k|^2 dt^2 / 4,
+//     u^{n+1} - 2u^n + u^{n-1} = (c1 - 2) u^n - c2 FFT(sin u^n),
+//     c1 - 2 = -4a/(1 + a),  c2 = dt^2/(1 + a).
+// The state is carried as u^n and the increment d^n = u^n - u^{n-1} in
+// physical space; only the small second difference goes through the
+// transforms.  (Forming u^{n+1} = c1 u^n - u^{n-1} through an FFT round trip
+// instead lets single-precision rounding that varies slowly from step to
+// step drive the slow modes, whose response grows like 1/theta^2 for a mode
+// rotating by theta per step.)
+//   column pass (half-width columns): W = iFFT_y((c1-2) FFT_y(U) - c2 FFT_y(S))
+//   row pass (pairs of real rows):    d^{n+1} = d^n + C2R_x(W);
+//                                     u^{n+1} = u^n + d^{n+1};
+//                                     U = R2C_x(u^{n+1}); S = R2C_x(sin u^{n+1})
+// The row pass's split leaves 2U, 2S; that factor and the unnormalised
+// transforms' 1/(nx ny) are folded into the column coefficients (sc).
+#include "kernels.hpp"
+#include "launch.hpp"
+
+namespace pst {
+
+// ENTRY: U, S from u_old and, if d_out != NULL, d_out = u_old - d_old (the
+//        increment from the two caller levels u_curr, u_prev).
+// STEP:  d_out = d_old + C2R(W), u_out = u_old + d_out, then U, S.
+// FINAL: d = alpha d_old + C2R(W), u_out = u_old + d, prev_out = u_old.
+enum { SG_ENTRY = 0, SG_STEP = 1, SG_FINAL = 2 };
+
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_row(
+    const cpx<T>* W, const T* u_old, const T* d_old, T alpha, T* u_out, T* d_out, T* prev_out,
+    cpx<T>* U, cpx<T>* S, int nlines, const cpx<T>* __restrict__ tw) {
+  using G = RowGeom<T, N>;
+  constexpr int H = N / 2 + 1;
+  extern __shared__ char smem[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
+  const int lid = threadIdx.x / G::TL, t = threadIdx.x % G::TL;
+  const int pair = blockIdx.x * G::LPB + lid;
+  const int la = 2 * pair, lb = 2 * pair + 1;
+  const bool va = la < nlines, vb = lb < nlines;
+  cpx<T>* L = lds + lid * lds_line_stride<T>(N);
+  const size_t ra = (size_t)la * N, rb = (size_t)lb * N;
+  cpx<T> u[G::R];
+  if constexpr (MODE == SG_ENTRY) {
+#pragma unroll
+    for (int s = 0; s < G::R; ++s) {
+      const int e = t + s * G::TL;
+      const T ua = va ? u_old[ra + e] : T(0), ub = vb ? u_old[rb + e] : T(0);
+      if (d_out != nullptr) {
+        if (va) d_out[ra + e] = ua - d_old[ra + e];
+        if (vb) d_out[rb + e] = ub - d_old[rb + e];
+      }
+      u[s] = cpx<T>{ua, ub};
+    }
+  } else {
+    load_pair_spectrum<T, N>(u, W + (size_t)la * H, W + (size_t)lb * H, t, va, vb, T(1));
+    line_fft<N, true>(u, L, t, tw);
+#pragma unroll
+    for (int s = 0; s < G::R; ++s) {
+      const int e = t + s * G::TL;
+      const T oa = va ? u_old[ra + e] : T(0), ob = vb ? u_old[rb + e] : T(0);
+      const T pa = va ? d_old[ra + e] : T(0), pb = vb ? d_old[rb + e] : T(0);
+      const T da = alpha * pa + u[s].re, db = alpha * pb + u[s].im;
+      u[s] = cpx<T>{oa + da, ob + db};
+      if constexpr (MODE == SG_FINAL) {
+        if (va) prev_out[ra + e] = oa;
+        if (vb) prev_out[rb + e] = ob;
+      } else {
+        if (va) d_out[ra + e] = da;
+        if (vb) d_out[rb + e] = db;
+      }
+      if (va) u_out[ra + e] = u[s].re;
+      if (vb) u_out[rb + e] = u[s].im;
+    }
+  }
+  if constexpr (MODE != SG_FINAL) {
+    cpx<T> sn[G::R];
+#pragma unroll
+    for (int s = 0; s < G::R; ++s) sn[s] = cpx<T>{sin(u[s].re), sin(u[s].im)};
+    line_fft<N, false>(u, L, t, tw);
+    store_pair_halves<T, N>(u, L, t, U + (size_t)la * H, U + (size_t)lb * H, va, vb);
+    line_fft<N, false>(sn, L, t, tw);
+    store_pair_halves<T, N>(sn, L, t, S + (size_t)la * H, S + (size_t)lb * H, va, vb);
+  }
+}
+
+// Column pass over the nx/2+1 half-spectrum columns.
+template <typename T, int N>
+__global__ __launch_bounds__(1024) void k_sg_col(const cpx<T>* U, const cpx<T>* S, cpx<T>* W, int ncols,
+                                                 int tiles_per_field, const cpx<T>* __restrict__ tw,
+                                                 T kx0, T ky0, T dt2q, T cnum, T c2num, T sc) {
+  using G = ColGeom<T, N>;
+  extern __shared__ char smem[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
+  const int Wt = blockDim.x / G::TL;
+  const int c = threadIdx.x % Wt, t = threadIdx.x / Wt;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int field = tile / tiles_per_field;
+  const int col = (tile % tiles_per_field) * Wt + c;
+  const bool valid = col < ncols;
+  const size_t off = (size_t)field * N * ncols + col;
+  cpx<T>* L = lds + c * lds_line_stride<T>(N);
+  cpx<T> u[G::R], s_[G::R];
+#pragma unroll
+  for (int s = 0; s < G::R; ++s) {
+    const size_t i = off + (size_t)(t + s * G::TL) * ncols;
+    u[s] = valid ? U[i] : cpx<T>{0, 0};
+    s_[s] = valid ? S[i] : cpx<T>{0, 0};
+  }
+  line_fft<N, false>(u, L, t, tw);
+  line_fft<N, false>(s_, L, t, tw);
+  const T kx = kx0 * (T)col;
+  const T kx2 = kx * kx;
+#pragma unroll
+  for (int s = 0; s < G::R; ++s) {
+    const int e = t + s * G::TL;
+    const T ky = ky0 * (T)(e < N / 2 ? e : e - N);
+    const T a = (kx2 + ky * ky) * dt2q;
+    const T inv = T(1) / (T(1) + a);
+    // step: c1 - 2 = -4a/(1+a) (cnum 2); start: c1 - 1 = -2a/(1+a) (cnum 1)
+    const T c1m = T(-2) * cnum * a * inv * sc, c2 = c2num * inv * sc;
+    u[s] = cpx<T>{c1m * u[s].re - c2 * s_[s].re, c1m * u[s].im - c2 * s_[s].im};
+  }
+  line_fft<N, true>(u, L, t, tw);
+  if (valid) {
+#pragma unroll
+    for (int s = 0; s < G::R; ++s) W[off + (size_t)(t + s * G::TL) * ncols] = u[s];
+  }
+}
+
+// ----------------------------------------------------------- Hamiltonian ---
+// Row pass: per row pair, sums of ((u1-u0)/dt)^2 -> part[4p], and of
+// sin^2(u1/2) + sin^2(u0/2) = ((1-cos u1) + (1-cos u0))/2 -> part[4p+1]
+// (double precision), and the x-transform of ubar = (u0+u1)/2 (times 2).
+template <typename T, int N>
+__global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_h_row(
+    const T* f0, const T* f1, cpx<T>* UB, double* part, int nlines, double inv_dt,
+    const cpx<T>* __restrict__ tw) {
+  using G = RowGeom<T, N>;
+  constexpr int H = N / 2 + 1;
+  extern __shared__ char smem[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
+  __shared__ double red[G::THREADS];
+  const int lid = threadIdx.x / G::TL, t = threadIdx.x % G::TL;
+  const int pair = blockIdx.x * G::LPB + lid;
+  const int la = 2 * pair, lb = 2 * pair + 1;
+  const bool va = la < nlines, vb = lb < nlines;
+  cpx<T>* L = lds + lid * lds_line_stride<T>(N);
+  cpx<T> ub[G::R];
+  double kin = 0.0, pot = 0.0;
+#pragma unroll
+  for (int s = 0; s < G::R; ++s) {
+    const int e = t + s * G::TL;
+    const double a0 = va ? (double)f0[(size_t)la * N + e] : 0.0, a1 = va ? (double)f1[(size_t)la * N + e] : 0.0;
+    const double b0 = vb ? (double)f0[(size_t)lb * N + e] : 0.0, b1 = vb ? (double)f1[(size_t)lb * N + e] : 0.0;
+    const double da = (a1 - a0) * inv_dt, db = (b1 - b0) * inv_dt;
+    kin += da * da + db * db;
+    const double sa0 = sin(0.5 * a0), sa1 = sin(0.5 * a1), sb0 = sin(0.5 * b0), sb1 = sin(0.5 * b1);
+    pot += sa0 * sa0 + sa1 * sa1 + sb0 * sb0 + sb1 * sb1;
+    ub[s] = cpx<T>{(T)(0.5 * (a0 + a1)), (T)(0.5 * (b0 + b1))};
+  }
+  kin = line_sum(red, lid, t, G::TL, kin);
+  pot = line_sum(red, lid, t, G::TL, pot);
+  if (t == 0 && va) {
+    part[4 * (size_t)pair] = kin;
+    part[4 * (size_t)pair + 1] = pot;
+  }
+  line_fft<N, false>(ub, L, t, tw);
+  store_pair_halves<T, N>(ub, L, t, UB + (size_t)la * H, UB + (size_t)lb * H, va, vb);
+}
+
+// Column pass: sum over the half spectrum of w(mx) |k|^2 |2 ubar_hat|^2 with
+// w = 1 on the self-conjugate columns mx = 0, nx/2 and 2 elsewhere.
+template <typename T, int N>
+__global__ __launch_bounds__(1024) void k_sg_h_col(cpx<T>* UB, double* part, int ncols, int nx,
+                                                   int tiles_per_field, const cpx<T>* __restrict__ tw,
+                                                   double kx0, double ky0) {
+  using G = ColGeom<T, N>;
+  extern __shared__ char smem[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
+  __shared__ double red[1024];
+  const int Wt = blockDim.x / G::TL;
+  const int c = threadIdx.x % Wt, t = threadIdx.x / Wt;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int field = tile / tiles_per_field;
+  const int col = (tile % tiles_per_field) * Wt + c;
+  const bool valid = col < ncols;
+  const size_t off = (size_t)field * N * ncols + col;
+  cpx<T>* L = lds + c * lds_line_stride<T>(N);
+  cpx<T> v[G::R];
+#pragma unroll
+  for (int s = 0; s < G::R; ++s) v[s] = valid ? UB[off + (size_t)(t + s * G::TL) * ncols] : cpx<T>{0, 0};
+  line_fft<N, false>(v, L, t, tw);
+  const double kx = kx0 * col;
+  const double w = (col == 0 || col == nx / 2) ? 1.0 : 2.0;
+  double acc = 0.0;
+#pragma unroll
+  for (int s = 0; s < G::R; ++s) {
+    const int e = t + s * G::TL;
+    const double ky = ky0 * (e < N / 2 ? e : e - N);
+    acc += (kx * kx + ky * ky) * ((double)v[s].re * v[s].re + (double)v[s].im * v[s].im);
+  }
+  acc = line_sum(red, c, t, G::TL, acc * w);
+  if (valid && t == 0) part[(size_t)field * ncols + col] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_sg_h_finish(int npairs, int ncols, const double* row_part,
+                                                     const double* col_part, double dxdy, double grad_coef,
+                                                     double* out, int* status) {
+  __shared__ double red[256];
+  const int f = blockIdx.x, t = threadIdx.x;
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int i = t; i < npairs; i += 256) {
+    a += row_part[4 * ((size_t)f * npairs + i)];
+    b += row_part[4 * ((size_t)f * npairs + i) + 1];
+  }
+  for (int i = t; i < ncols; i += 256) c += col_part[(size_t)f * ncols + i];
+  a = line_sum(red, 0, t, 256, a);
+  b = line_sum(red, 0, t, 256, b);
+  c = line_sum(red, 0, t, 256, c);
+  if (t == 0) {
+    const double kin = 0.5 * dxdy * a, pot = dxdy * b, grad = grad_coef * c;
+    out[4 * f + 0] = kin + grad + pot;
+    out[4 * f + 1] = kin;
+    out[4 * f + 2] = grad;
+    out[4 * f + 3] = pot;
+    if (!isfinite(kin + grad + pot)) atomicOr(status, (int)ST_NONFINITE);
+  }
+}
+
+// ----------------------------------------------------------- launchers ---
+template <typename T>
+static hipError_t row(int mode, int nx, int nlines, const void* W, const void* u_old, const void* d_old,
+                      double alpha, void* u_out, void* d_out, void* prev_out, void* U, void* S, const void* tw,
+                      hipStream_t s) {
+  bool ok = dispatch_n(nx, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    using G = RowGeom<T, N>;
+    const int grid = ((nlines + 1) / 2 + G::LPB - 1) / G::LPB;
+    auto go = [&](auto kern) {
+      allow_lds(kern, G::LDS_BYTES);
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(G::THREADS), G::LDS_BYTES, s, (const cpx<T>*)W, (const T*)u_old,
+                         (const T*)d_old, (T)alpha, (T*)u_out, (T*)d_out, (T*)prev_out, (cpx<T>*)U, (cpx<T>*)S,
+                         nlines, (const cpx<T>*)tw);
+    };
+    if (mode == SG_ENTRY) go(k_sg_row<T, N, SG_ENTRY>);
+    else if (mode == SG_STEP) go(k_sg_row<T, N, SG_STEP>);
+    else go(k_sg_row<T, N, SG_FINAL>);
+  });
+  return ok ? hipGetLastError() : hipErrorInvalidValue;
+}
+
+hipError_t sg_row(Prec p, int mode, int nx, int nlines, const void* W, const void* u_old, const void* d_old,
+                  double alpha, void* u_out, void* d_out, void* prev_out, void* U, void* S, const void* tw,
+                  hipStream_t s) {
+  return p == P32 ? row<float>(mode, nx, nlines, W, u_old, d_old, alpha, u_out, d_out, prev_out, U, S, tw, s)
+                  : row<double>(mode, nx, nlines, W, u_old, d_old, alpha, u_out, d_out, prev_out, U, S, tw, s);
+}
+
+template <typename T>
+static hipError_t col(int ny, int nx, int nfields, const void* U, const void* S, void* W, const void* tw,
+                      double kx0, double ky0, double dt2q, double cnum, double c2num, double sc, int Wt,
+                      hipStream_t s) {
+  bool ok = dispatch_n(ny, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    using G = ColGeom<T, N>;
+    const int ncols = nx / 2 + 1;
+    const int tiles = (ncols + Wt - 1) / Wt;
+    allow_lds(k_sg_col<T, N>, G::lds_bytes(Wt));
+    hipLaunchKernelGGL((k_sg_col<T, N>), dim3(tiles * nfields), dim3(Wt * G::TL), G::lds_bytes(Wt), s,
+                       (const cpx<T>*)U, (const cpx<T>*)S, (cpx<T>*)W, ncols, tiles, (const cpx<T>*)tw,
+                       (T)kx0, (T)ky0, (T)dt2q, (T)cnum, (T)c2num, (T)sc);
+  });
+  return ok ? hipGetLastError() : hipErrorInvalidValue;
+}
+
+hipError_t sg_col(Prec p, int ny, int nx, int nfields, const void* U, const void* S, void* W, const void* tw,
+                  double kx0, double ky0, double dt2q, double cnum, double c2num, double sc, int Wt,
+                  hipStream_t s) {
+  return p == P32 ? col<float>(ny, nx, nfields, U, S, W, tw, kx0, ky0, dt2q, cnum, c2num, sc, Wt, s)
+                  : col<double>(ny, nx, nfields, U, S, W, tw, kx0, ky0, dt2q, cnum, c2num, sc, Wt, s);
+}
+
+template <typename T>
+static hipError_t hrow(int nx, int nlines, const void* f0, const void* f1, void* UB, double* part,
+                       double inv_dt, const void* tw, hipStream_t s) {
+  bool ok = dispatch_n(nx, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    using G = RowGeom<T, N>;
+    const int grid = ((nlines + 1) / 2 + G::LPB - 1) / G::LPB;
+    allow_lds(k_sg_h_row<T, N>, G::LDS_BYTES);
+    hipLaunchKernelGGL((k_sg_h_row<T, N>), dim3(grid), dim3(G::THREADS), G::LDS_BYTES, s, (const T*)f0,
+                       (const T*)f1, (cpx<T>*)UB, part, nlines, inv_dt, (const cpx<T>*)tw);
+  });
+  return ok ? hipGetLastError() : hipErrorInvalidValue;
+}
+
+hipError_t sg_h_row(Prec p, int nx, int nlines, const void* f0, const void* f1, void* UB, double* part,
+                    double inv_dt, const void* tw, hipStream_t s) {
+  return p == P32 ? hrow<float>(nx, nlines, f0, f1, UB, part, inv_dt, tw, s)
+                  : hrow<double>(nx, nlines, f0, f1, UB, part, inv_dt, tw, s);
+}
+
+template <typename T>
+static hipError_t hcol(int ny, int nx, int nfields, void* UB, double* part, const void* tw, double kx0,
+                       double ky0, int Wt, hipStream_t s) {
+  bool ok = dispatch_n(ny, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    using G = ColGeom<T, N>;
+    const int ncols = nx / 2 + 1;
+    const int tiles = (ncols + Wt - 1) / Wt;
+    allow_lds(k_sg_h_col<T, N>, G::lds_bytes(Wt));
+    hipLaunchKernelGGL((k_sg_h_col<T, N>), dim3(tiles * nfields), dim3(Wt * G::TL), G::lds_bytes(Wt), s,
+                       (cpx<T>*)UB, part, ncols, nx, tiles, (const cpx<T>*)tw, kx0, ky0);
+  });
+  return ok ? hipGetLastError() : hipErrorInvalidValue;
+}
+
+hipError_t sg_h_col(Prec p, int ny, int nx, int nfields, void* UB, double* part, const void* tw, double kx0,
+                    double ky0, int Wt, hipStream_t s) {
+  return p == P32 ? hcol<float>(ny, nx, nfields, UB, part, tw, kx0, ky0, Wt, s)
+                  : hcol<double>(ny, nx, nfields, UB, part, tw, kx0, ky0, Wt, s);
+}
+
+hipError_t sg_h_finish(int nfields, int npairs, int ncols, const double* row_part, const double* col_part,
+                       double dxdy, double grad_coef, double* out, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_sg_h_finish, dim3(nfields), dim3(256), 0, s, npairs, ncols, row_part, col_part, dxdy,
+                     grad_coef, out, status);
+  return hipGetLastError();
+}
+
+}  // namespace pst

@@ -106,6 +106,62 @@ inline void allow_lds(K kernel, size_t bytes) {
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// ------------------------------------------------------ real row pairs ---
+// Two real rows a, b travel as one complex line z = a + i b.
+
+// Gather z's spectrum from the half spectra A, B (n/2+1 entries each) of
+// rows a and b: Z[k] = A[k] + i B[k], Z[n-k] = conj(A[k]) + i conj(B[k]).
+// The imaginary parts of the self-conjugate modes k = 0, n/2 are ignored,
+// as an inverse real transform does.  Missing rows read as zero.
+template <typename T, int N>
+__device__ __forceinline__ void load_pair_spectrum(cpx<T> (&v)[line_radix(N)], const cpx<T>* A,
+                                                   const cpx<T>* B, int t, bool va, bool vb,
+                                                   T scale) {
+  constexpr int TL = N / line_radix(N);
+#pragma unroll
+  for (int s = 0; s < line_radix(N); ++s) {
+    const int e = t + s * TL;
+    const bool lo = e <= N / 2;
+    const int k = lo ? e : N - e;
+    cpx<T> a = va ? A[k] : cpx<T>{0, 0};
+    cpx<T> b = vb ? B[k] : cpx<T>{0, 0};
+    if (e == 0 || e == N / 2) {
+      a.im = 0;
+      b.im = 0;
+    }
+    if (!lo) {
+      a = conj(a);
+      b = conj(b);
+    }
+    v[s] = (a + mul_i(b)) * scale;
+  }
+}
+
+// After the forward transform Z of z = a + i b (natural order in v), store
+// 2*A[k] = Z[k] + conj(Z[n-k]) and 2*B[k] = -i (Z[k] - conj(Z[n-k])) for
+// k = 0..n/2 (the half spectra of rows a and b, times 2).  Uses the line's
+// LDS buffer; contains block barriers.
+template <typename T, int N>
+__device__ __forceinline__ void store_pair_halves(const cpx<T> (&v)[line_radix(N)], cpx<T>* L, int t,
+                                                  cpx<T>* A, cpx<T>* B, bool va, bool vb) {
+  constexpr int R = line_radix(N);
+  constexpr int TL = N / R;
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < R; ++s) L[lds_idx(t + s * TL)] = v[s];
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s <= R / 2; ++s) {
+    if (s == R / 2 && t != 0) break;
+    const int k = (s < R / 2) ? t + s * TL : N / 2;
+    const cpx<T> zk = L[lds_idx(k)];
+    const cpx<T> zm = conj(L[lds_idx((N - k) & (N - 1))]);
+    const cpx<T> sum = zk + zm, dif = zk - zm;
+    if (va) A[k] = sum;
+    if (vb) B[k] = cpx<T>{dif.im, -dif.re};
+  }
+}
+
 // ---------------------------------------------------------- N dispatch ---
 template <int N>
 using IntC = std::integral_constant<int, N>;

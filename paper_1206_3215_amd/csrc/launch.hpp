@@ -41,7 +41,7 @@ hipError_t fft_row_c2r(Prec p, int n, int nlines, const void* in, void* out, dou
 // 2: psi = iFFT_x(H) / nx.  phase_coef = g dt / nx^2, scale as stated.
 hipError_t nls_row(Prec p, int nx, int nlines, void* psi, int mode, double phase_coef,
                    double scale, const void* tw, hipStream_t s);
-// Column: FFT_y, multiply by ex[mx]*ey[my], iFFT_y (in place).
+// Column: FFT_y, multiply by (1 + ex[mx]) (1 + ey[my]) / (nx ny), iFFT_y (in place).
 hipError_t nls_col(Prec p, int ny, int nx, int nfields, void* psi, const void* tw,
                    const void* ex, const void* ey, int W, hipStream_t s);
 
@@ -58,5 +58,61 @@ hipError_t nls_cq_col(Prec p, int ny, int nx, int nfields, void* spec, double* p
 hipError_t nls_cq_finish(int nfields, int ny, int nx, const double* row_part,
                          const double* col_part, double dxdy, double kin_coef, double g,
                          double* out, int* status, hipStream_t s);
+
+// ------------------------------------------------------------------ SG ---
+// Row pass over row pairs (increment form, see k_sg.hip):
+//   mode 0 (entry): U, S = 2 R2C_x(u_old), 2 R2C_x(sin u_old); if d_out is
+//                   not NULL, d_out = u_old - d_old.
+//   mode 1 (step):  d_out = d_old + C2R_x(W); u_out = u_old + d_out; U, S.
+//   mode 2 (final): d = alpha d_old + C2R_x(W); u_out = u_old + d;
+//                   prev_out = u_old.
+// Each element is read before it is written, so outputs may alias inputs.
+hipError_t sg_row(Prec p, int mode, int nx, int nlines, const void* W, const void* u_old, const void* d_old,
+                  double alpha, void* u_out, void* d_out, void* prev_out, void* U, void* S, const void* tw,
+                  hipStream_t s);
+// Column pass: W = iFFT_y(c1m FFT_y(U) - c2 FFT_y(S)) with a = |k|^2 dt2q,
+// c1m = -2 cnum a/(1+a) sc, c2 = c2num/(1+a) sc.
+hipError_t sg_col(Prec p, int ny, int nx, int nfields, const void* U, const void* S, void* W, const void* tw,
+                  double kx0, double ky0, double dt2q, double cnum, double c2num, double sc, int Wt,
+                  hipStream_t s);
+// Hamiltonian H^{n+1/2}(f0 = u^n, f1 = u^{n+1}).
+hipError_t sg_h_row(Prec p, int nx, int nlines, const void* f0, const void* f1, void* UB, double* part,
+                    double inv_dt, const void* tw, hipStream_t s);
+hipError_t sg_h_col(Prec p, int ny, int nx, int nfields, void* UB, double* part, const void* tw, double kx0,
+                    double ky0, int Wt, hipStream_t s);
+hipError_t sg_h_finish(int nfields, int npairs, int ncols, const double* row_part, const double* col_part,
+                       double dxdy, double grad_coef, double* out, int* status, hipStream_t s);
+
+// ------------------------------------------------------------------ NS ---
+struct NsPtrs {
+  const void* NH;  // Jacobian hybrid (times 2), or omega's x-transform at entry
+  void* WN;        // w^n spectrum
+  void* Q;         // -2h w^n - dt/2 N(w^n)
+  void* DK;        // increment d^k = w^k - w^n
+  void* D;         // 4 derivative hybrids, dstride complex apart
+  size_t dstride;
+  void* OUT;       // exit: iFFT_y(w^n + d) hybrid
+  double* part;    // 2 doubles per column: residual, |w|^2
+};
+struct NsScalars {
+  double kx0, ky0, hnu, qdt, nscale, dscale;
+  int nx, kx_cut, ky_cut;
+};
+// Row pass: Jacobian of the derivative hybrids -> NH.  Blocks whose fields
+// are all done (done != NULL) return at once.
+hipError_t ns_row(Prec p, int nx, int nlines, int ny, const void* D, size_t dstride, void* NH, const int* done,
+                  const void* tw, hipStream_t s);
+// Column pass, mode 0 entry / 1 first iteration / 2 later iteration / 3 exit.
+hipError_t ns_col(Prec p, int mode, int ny, int nfields, const NsPtrs& P, const NsScalars& S, const int* done,
+                  const void* tw, int Wt, hipStream_t s);
+// Convergence bookkeeping per field (see k_ns_finish).
+hipError_t ns_finish(int nfields, int ncols, const double* part, double vol, double tol, double fp_floor,
+                     int max_iter, int fixed, int first, int* done, int* iters, int* iters_out, double* resid,
+                     int* status, hipStream_t s);
+// Diagnostics from omega's x-transform XH: energy and enstrophy.
+hipError_t ns_cq_col(Prec p, int ny, int nx, int nfields, const void* XH, double* part, double kx0, double ky0,
+                     const void* tw, int Wt, hipStream_t s);
+hipError_t ns_cq_finish(int nfields, int ncols, const double* part, double en_coef, double zz_coef, double* out,
+                        int* status, hipStream_t s);
 
 }  // namespace pst

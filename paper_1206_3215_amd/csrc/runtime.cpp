@@ -55,19 +55,30 @@ static std::vector<std::complex<double>> twiddles(int n) {
   return tab;
 }
 
-// Round a unit-modulus complex number to single precision: of the four
-// pairs of neighbouring floats (each component rounded down or up), take the
-// one whose modulus is closest to 1.  Each component stays within one ulp,
-// and the systematic growth or decay that rounded unit factors would apply
-// at every step is avoided.
+// Round a unit-modulus complex number to single precision: among the float
+// pairs within two ulps of (cos, sin) whose angle is within 6e-8 rad of the
+// exact one, take the pair whose modulus is closest to 1 (nearest rounding
+// gives |w|^2 - 1 up to ~6e-8).  FFT round trips then carry no systematic
+// gain, which would otherwise act at every time step.
 static void round_unit(std::complex<double> z, float* re, float* im) {
-  const double a = z.real(), b = z.imag();
-  const float a0 = (float)a, b0 = (float)b;
-  const float ac[2] = {a0, (double)a0 > a ? std::nextafter(a0, -2.0f) : std::nextafter(a0, 2.0f)};
-  const float bc[2] = {b0, (double)b0 > b ? std::nextafter(b0, -2.0f) : std::nextafter(b0, 2.0f)};
+  const double a = z.real(), b = z.imag(), ang0 = std::atan2(b, a);
+  float ac[5], bc[5];
+  ac[0] = (float)a;
+  bc[0] = (float)b;
+  for (int i = 1; i <= 2; ++i) {
+    ac[2 * i - 1] = std::nextafter(ac[2 * i - 3 < 0 ? 0 : 2 * i - 3], -2.0f);
+    ac[2 * i] = std::nextafter(ac[2 * i - 2], 2.0f);
+    bc[2 * i - 1] = std::nextafter(bc[2 * i - 3 < 0 ? 0 : 2 * i - 3], -2.0f);
+    bc[2 * i] = std::nextafter(bc[2 * i - 2], 2.0f);
+  }
   double best = 1e300;
+  *re = ac[0];
+  *im = bc[0];
   for (float x : ac)
     for (float y : bc) {
+      double da = std::atan2((double)y, (double)x) - ang0;
+      da = std::remainder(da, 2.0 * M_PI);
+      if (std::fabs(da) > 6e-8) continue;
       const double e = std::fabs((double)x * x + (double)y * y - 1.0);
       if (e < best) {
         best = e;
@@ -156,9 +167,11 @@ size_t ws_layout(Plan* pl) {
     pl->off_spec = take(B * ny * h * pl->csize);
     pl->off_spec2 = take(B * ny * h * pl->csize);
     pl->off_spec3 = take(B * ny * h * pl->csize);
+    pl->off_spec4 = take(B * ny * h * pl->csize);
     pl->off_hyb = take(4 * B * ny * h * pl->csize);
     pl->off_rowpart = take(B * ny * 4 * sizeof(double));
     pl->off_colpart = take(B * h * 4 * sizeof(double));
+    pl->off_nsstate = take(B * (2 * sizeof(int) + sizeof(double)) + 64);
   }
   return off;
 }

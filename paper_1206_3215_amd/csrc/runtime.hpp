@@ -14,10 +14,10 @@
 struct NlsTables {
   bool valid = false;
   double dt = 0, lx = 0, ly = 0;
-  void* ex_half = nullptr;  // exp(-i kx^2 dt/2)
-  void* ex_full = nullptr;  // exp(-i kx^2 dt)
-  void* ey_half = nullptr;  // exp(-i ky^2 dt/2) / (nx ny)
-  void* ey_full = nullptr;  // exp(-i ky^2 dt) / (nx ny)
+  void* ex_half = nullptr;  // exp(-i kx^2 dt/2) - 1
+  void* ex_full = nullptr;  // exp(-i kx^2 dt) - 1
+  void* ey_half = nullptr;  // exp(-i ky^2 dt/2) - 1
+  void* ey_full = nullptr;  // exp(-i ky^2 dt) - 1
 };
 
 struct pst_plan_s {
@@ -38,7 +38,9 @@ struct pst_plan_s {
   void* ws = nullptr;
   bool ws_owned = false;
   size_t ws_need = 0;
-  size_t off_spec = 0, off_spec2 = 0, off_spec3 = 0, off_hyb = 0, off_rowpart = 0, off_colpart = 0;
+  size_t off_spec = 0, off_spec2 = 0, off_spec3 = 0, off_spec4 = 0, off_hyb = 0, off_rowpart = 0,
+         off_colpart = 0, off_nsstate = 0;
+  int ns_guess = 3;  // predicted fixed-point iterations for the next step
   NlsTables nls;
   // per-pass timing (pst_profile_enable)
   bool prof = false;
