@@ -194,5 +194,42 @@ class Plan:
         return s.value
 
 
+def make_params(eq: str, d, dt: float, g: float = 1.0, nu: float = 0.0, tol: float = 1e-10,
+                max_iter: int = 50, fixed_iters: int = 0):
+    if eq == "nls":
+        return NlsParams(domain(d), dt, g)
+    if eq == "sg":
+        return SgParams(domain(d), dt)
+    return NsParams(domain(d), dt, nu, tol, max_iter, fixed_iters)
+
+
+def solve_batch(requests, stream=None) -> None:
+    """Advance independent simulations in one call.
+
+    requests: sequence of dicts with keys eq ("nls" | "sg" | "ns"), f0, f1
+    (torch tensors; f1 only for "sg"), params (from make_params), nsteps,
+    and optionally dev_status (a CUDA int32 tensor of one element).
+    Fields keep their own storage; the library groups them by equation,
+    size, precision and parameters.
+    """
+    import torch
+    arr = (Request * len(requests))()
+    keep = []
+    for i, r in enumerate(requests):
+        f0 = r["f0"]
+        prec = PST_FP64 if f0.dtype in (torch.float64, torch.complex128) else PST_FP32
+        ny, nx = f0.shape[-2:]
+        pr = r["params"]
+        keep.append(pr)
+        arr[i].eq = EQ[r["eq"]]
+        arr[i].nx, arr[i].ny, arr[i].prec, arr[i].nsteps = nx, ny, prec, int(r["nsteps"])
+        arr[i].params = C.cast(C.pointer(pr), C.c_void_p)
+        arr[i].f0 = _ptr(f0)
+        arr[i].f1 = _ptr(r.get("f1"))
+        arr[i].dev_status = _ptr(r.get("dev_status"))
+    st = stream if stream is not None else torch.cuda.current_stream()
+    check(lib.solve_batch(arr, len(requests), _vp(st.cuda_stream)), "solve_batch")
+
+
 def version() -> str:
     return lib.pst_version().decode()

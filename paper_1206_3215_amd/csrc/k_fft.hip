@@ -58,7 +58,7 @@ __global__ __launch_bounds__(1024) void k_col_c2c(const cpx<T>* src, cpx<T>* dst
 // Rows 2p and 2p+1 travel as one complex line z = a + i b.
 template <typename T, int N>
 __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_row_r2c(
-    const T* in, cpx<T>* out, int nlines, const cpx<T>* __restrict__ tw) {
+    FieldRef in, cpx<T>* out, int nlines, int lny, const cpx<T>* __restrict__ tw) {
   using G = RowGeom<T, N>;
   constexpr int H = N / 2 + 1;
   extern __shared__ char smem[];
@@ -69,8 +69,9 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_row_r2c(
   const bool va = la < nlines, vb = lb < nlines;
   cpx<T>* L = lds + lid * lds_line_stride<T>(N);
   cpx<T> v[G::R];
-  const T* ra = in + (size_t)la * N;
-  const T* rb = in + (size_t)lb * N;
+  const int ny = 1 << lny;
+  const T* ra = (const T*)in.at(la >> lny) + (size_t)(la & (ny - 1)) * N;
+  const T* rb = ra + N;
 #pragma unroll
   for (int s = 0; s < G::R; ++s) {
     const int e = t + s * G::TL;
@@ -96,7 +97,7 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_row_r2c(
 
 template <typename T, int N>
 __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_row_c2r(
-    const cpx<T>* in, T* out, int nlines, T scale, const cpx<T>* __restrict__ tw) {
+    const cpx<T>* in, FieldRef out, int nlines, int lny, T scale, const cpx<T>* __restrict__ tw) {
   using G = RowGeom<T, N>;
   constexpr int H = N / 2 + 1;
   extern __shared__ char smem[];
@@ -127,8 +128,9 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_row_c2r(
     v[s] = A + mul_i(B);
   }
   line_fft<N, true>(v, L, t, tw);
-  T* oa = out + (size_t)la * N;
-  T* ob = out + (size_t)lb * N;
+  const int ny = 1 << lny;
+  T* oa = (T*)out.at(la >> lny) + (size_t)(la & (ny - 1)) * N;
+  T* ob = oa + N;
 #pragma unroll
   for (int s = 0; s < G::R; ++s) {
     const int e = t + s * G::TL;
@@ -195,7 +197,7 @@ hipError_t fft_col_c2c(Prec p, int ny, int ncols, int ld, int nfields, const voi
 }
 
 template <typename T>
-static hipError_t row_r2c(int n, int nlines, const void* in, void* out, const void* tw,
+static hipError_t row_r2c(int n, int nlines, int ny, FieldRef in, void* out, const void* tw,
                           hipStream_t s) {
   bool ok = dispatch_n(n, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
@@ -204,19 +206,19 @@ static hipError_t row_r2c(int n, int nlines, const void* in, void* out, const vo
     const int grid = (pairs + G::LPB - 1) / G::LPB;
     allow_lds((k_row_r2c<T, N>), G::LDS_BYTES);
     hipLaunchKernelGGL((k_row_r2c<T, N>), dim3(grid), dim3(G::THREADS), G::LDS_BYTES, s,
-                       (const T*)in, (cpx<T>*)out, nlines, (const cpx<T>*)tw);
+                       in, (cpx<T>*)out, nlines, ilog2c(ny), (const cpx<T>*)tw);
   });
   return ok ? hipGetLastError() : hipErrorInvalidValue;
 }
 
-hipError_t fft_row_r2c(Prec p, int n, int nlines, const void* in, void* out, const void* tw,
+hipError_t fft_row_r2c(Prec p, int n, int nlines, int ny, FieldRef in, void* out, const void* tw,
                        hipStream_t s) {
-  return p == P32 ? row_r2c<float>(n, nlines, in, out, tw, s) : row_r2c<double>(n, nlines, in, out, tw, s);
+  return p == P32 ? row_r2c<float>(n, nlines, ny, in, out, tw, s) : row_r2c<double>(n, nlines, ny, in, out, tw, s);
 }
 
 template <typename T>
-static hipError_t row_c2r(int n, int nlines, const void* in, void* out, double scale, const void* tw,
-                          hipStream_t s) {
+static hipError_t row_c2r(int n, int nlines, int ny, const void* in, FieldRef out, double scale,
+                          const void* tw, hipStream_t s) {
   bool ok = dispatch_n(n, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
     using G = RowGeom<T, N>;
@@ -224,15 +226,15 @@ static hipError_t row_c2r(int n, int nlines, const void* in, void* out, double s
     const int grid = (pairs + G::LPB - 1) / G::LPB;
     allow_lds((k_row_c2r<T, N>), G::LDS_BYTES);
     hipLaunchKernelGGL((k_row_c2r<T, N>), dim3(grid), dim3(G::THREADS), G::LDS_BYTES, s,
-                       (const cpx<T>*)in, (T*)out, nlines, (T)scale, (const cpx<T>*)tw);
+                       (const cpx<T>*)in, out, nlines, ilog2c(ny), (T)scale, (const cpx<T>*)tw);
   });
   return ok ? hipGetLastError() : hipErrorInvalidValue;
 }
 
-hipError_t fft_row_c2r(Prec p, int n, int nlines, const void* in, void* out, double scale,
+hipError_t fft_row_c2r(Prec p, int n, int nlines, int ny, const void* in, FieldRef out, double scale,
                        const void* tw, hipStream_t s) {
-  return p == P32 ? row_c2r<float>(n, nlines, in, out, scale, tw, s)
-                  : row_c2r<double>(n, nlines, in, out, scale, tw, s);
+  return p == P32 ? row_c2r<float>(n, nlines, ny, in, out, scale, tw, s)
+                  : row_c2r<double>(n, nlines, ny, in, out, scale, tw, s);
 }
 
 int col_tile_max(Prec p, int n) {

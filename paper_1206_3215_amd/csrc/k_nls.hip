@@ -21,7 +21,7 @@ namespace pst {
 
 template <typename T, int N, int MODE>
 __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_nls_row(
-    cpx<T>* psi, int nlines, T phase_coef, T scale, const cpx<T>* __restrict__ tw) {
+    FieldRef psi, int nlines, int lny, T phase_coef, T scale, const cpx<T>* __restrict__ tw) {
   using G = RowGeom<T, N>;
   extern __shared__ char smem[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
@@ -29,7 +29,7 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_nls_row(
   const int line = blockIdx.x * G::LPB + lid;
   const bool valid = line < nlines;
   cpx<T>* L = lds + lid * lds_line_stride<T>(N);
-  cpx<T>* g = psi + (size_t)line * N;
+  cpx<T>* g = (cpx<T>*)psi.at(line >> lny) + (size_t)(line & ((1 << lny) - 1)) * N;
   cpx<T> v[G::R];
 #pragma unroll
   for (int s = 0; s < G::R; ++s) v[s] = valid ? g[t + s * G::TL] : cpx<T>{0, 0};
@@ -54,7 +54,7 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_nls_row(
 }
 
 template <typename T, int N>
-__global__ __launch_bounds__(1024) void k_nls_col(cpx<T>* psi, int nx, int tiles_per_field,
+__global__ __launch_bounds__(1024) void k_nls_col(FieldRef psi, int nx, int tiles_per_field,
                                                   const cpx<T>* __restrict__ tw,
                                                   const cpx<T>* __restrict__ ex,
                                                   const cpx<T>* __restrict__ ey, T scale) {
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(1024) void k_nls_col(cpx<T>* psi, int nx, int tiles
   const int field = tile / tiles_per_field;
   const int col = (tile % tiles_per_field) * W + c;
   const bool valid = col < nx;
-  cpx<T>* base = psi + (size_t)field * N * nx + col;
+  cpx<T>* base = (cpx<T>*)psi.at(field) + col;
   cpx<T>* L = lds + c * lds_line_stride<T>(N);
   cpx<T> v[G::R];
 #pragma unroll
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(1024) void k_nls_col(cpx<T>* psi, int nx, int tiles
 }
 
 template <typename T>
-static hipError_t row(int nx, int nlines, void* psi, int mode, double pc, double scale,
+static hipError_t row(int nx, int nlines, int ny, FieldRef psi, int mode, double pc, double scale,
                       const void* tw, hipStream_t s) {
   bool ok = dispatch_n(nx, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
@@ -97,28 +97,28 @@ static hipError_t row(int nx, int nlines, void* psi, int mode, double pc, double
     if (mode == 0) {
       allow_lds((k_nls_row<T, N, 0>), G::LDS_BYTES);
       hipLaunchKernelGGL((k_nls_row<T, N, 0>), dim3(grid), dim3(G::THREADS), G::LDS_BYTES, s,
-                         (cpx<T>*)psi, nlines, (T)pc, (T)scale, (const cpx<T>*)tw);
+                         psi, nlines, ilog2c(ny), (T)pc, (T)scale, (const cpx<T>*)tw);
     } else if (mode == 1) {
       allow_lds((k_nls_row<T, N, 1>), G::LDS_BYTES);
       hipLaunchKernelGGL((k_nls_row<T, N, 1>), dim3(grid), dim3(G::THREADS), G::LDS_BYTES, s,
-                         (cpx<T>*)psi, nlines, (T)pc, (T)scale, (const cpx<T>*)tw);
+                         psi, nlines, ilog2c(ny), (T)pc, (T)scale, (const cpx<T>*)tw);
     } else {
       allow_lds((k_nls_row<T, N, 2>), G::LDS_BYTES);
       hipLaunchKernelGGL((k_nls_row<T, N, 2>), dim3(grid), dim3(G::THREADS), G::LDS_BYTES, s,
-                         (cpx<T>*)psi, nlines, (T)pc, (T)scale, (const cpx<T>*)tw);
+                         psi, nlines, ilog2c(ny), (T)pc, (T)scale, (const cpx<T>*)tw);
     }
   });
   return ok ? hipGetLastError() : hipErrorInvalidValue;
 }
 
-hipError_t nls_row(Prec p, int nx, int nlines, void* psi, int mode, double phase_coef, double scale,
+hipError_t nls_row(Prec p, int nx, int nlines, int ny, FieldRef psi, int mode, double phase_coef, double scale,
                    const void* tw, hipStream_t s) {
-  return p == P32 ? row<float>(nx, nlines, psi, mode, phase_coef, scale, tw, s)
-                  : row<double>(nx, nlines, psi, mode, phase_coef, scale, tw, s);
+  return p == P32 ? row<float>(nx, nlines, ny, psi, mode, phase_coef, scale, tw, s)
+                  : row<double>(nx, nlines, ny, psi, mode, phase_coef, scale, tw, s);
 }
 
 template <typename T>
-static hipError_t col(int ny, int nx, int nfields, void* psi, const void* tw, const void* ex,
+static hipError_t col(int ny, int nx, int nfields, FieldRef psi, const void* tw, const void* ex,
                       const void* ey, int W, hipStream_t s) {
   bool ok = dispatch_n(ny, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
@@ -126,13 +126,13 @@ static hipError_t col(int ny, int nx, int nfields, void* psi, const void* tw, co
     const int tiles = (nx + W - 1) / W;
     allow_lds((k_nls_col<T, N>), G::lds_bytes(W));
     hipLaunchKernelGGL((k_nls_col<T, N>), dim3(tiles * nfields), dim3(W * G::TL), G::lds_bytes(W), s,
-                       (cpx<T>*)psi, nx, tiles, (const cpx<T>*)tw, (const cpx<T>*)ex,
+                       psi, nx, tiles, (const cpx<T>*)tw, (const cpx<T>*)ex,
                        (const cpx<T>*)ey, (T)(1.0 / ((double)nx * N)));
   });
   return ok ? hipGetLastError() : hipErrorInvalidValue;
 }
 
-hipError_t nls_col(Prec p, int ny, int nx, int nfields, void* psi, const void* tw, const void* ex,
+hipError_t nls_col(Prec p, int ny, int nx, int nfields, FieldRef psi, const void* tw, const void* ex,
                    const void* ey, int W, hipStream_t s) {
   return p == P32 ? col<float>(ny, nx, nfields, psi, tw, ex, ey, W, s)
                   : col<double>(ny, nx, nfields, psi, tw, ex, ey, W, s);

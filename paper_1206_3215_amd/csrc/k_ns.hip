@@ -209,7 +209,7 @@ __global__ __launch_bounds__(1024) void k_ns_col(const cpx<T>* NH, cpx<T>* WN, c
 __global__ __launch_bounds__(256) void k_ns_finish(int ncols, const double* part, double vol, double tol,
                                                    double fp_floor, int max_iter, int fixed, int first,
                                                    int* done, int* iters, int* iters_out, double* resid,
-                                                   int* status) {
+                                                   int* status, int* const* fstat) {
   __shared__ double red[256];
   const int f = blockIdx.x, t = threadIdx.x;
   if (!first && done[f]) return;
@@ -233,6 +233,7 @@ __global__ __launch_bounds__(256) void k_ns_finish(int ncols, const double* part
       if (!fin && it >= max_iter) {
         fin = true;
         atomicOr(status, (int)ST_NOT_CONVERGED);
+        if (fstat != nullptr && fstat[f] != nullptr) atomicOr(fstat[f], (int)ST_NOT_CONVERGED);
       }
     }
     if (!isfinite(res)) {
@@ -358,9 +359,9 @@ hipError_t ns_col(Prec p, int mode, int ny, int nfields, const NsPtrs& P, const 
 
 hipError_t ns_finish(int nfields, int ncols, const double* part, double vol, double tol, double fp_floor,
                      int max_iter, int fixed, int first, int* done, int* iters, int* iters_out, double* resid,
-                     int* status, hipStream_t s) {
+                     int* status, int* const* fstat, hipStream_t s) {
   hipLaunchKernelGGL(k_ns_finish, dim3(nfields), dim3(256), 0, s, ncols, part, vol, tol, fp_floor, max_iter, fixed,
-                     first, done, iters, iters_out, resid, status);
+                     first, done, iters, iters_out, resid, status, fstat);
   return hipGetLastError();
 }
 

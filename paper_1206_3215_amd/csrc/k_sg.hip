@@ -28,8 +28,8 @@ enum { SG_ENTRY = 0, SG_STEP = 1, SG_FINAL = 2 };
 
 template <typename T, int N, int MODE>
 __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_row(
-    const cpx<T>* W, const T* u_old, const T* d_old, T alpha, T* u_out, T* d_out, T* prev_out,
-    cpx<T>* U, cpx<T>* S, int nlines, const cpx<T>* __restrict__ tw) {
+    const cpx<T>* W, FieldRef u_old_f, FieldRef d_old_f, T alpha, FieldRef u_out_f, FieldRef d_out_f,
+    FieldRef prev_out_f, cpx<T>* U, cpx<T>* S, int nlines, int lny, const cpx<T>* __restrict__ tw) {
   using G = RowGeom<T, N>;
   constexpr int H = N / 2 + 1;
   extern __shared__ char smem[];
@@ -39,14 +39,21 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_row(
   const int la = 2 * pair, lb = 2 * pair + 1;
   const bool va = la < nlines, vb = lb < nlines;
   cpx<T>* L = lds + lid * lds_line_stride<T>(N);
-  const size_t ra = (size_t)la * N, rb = (size_t)lb * N;
+  // rows a, b are rows y, y+1 of field f; offsets are relative to each field
+  const int f = la >> lny;
+  const size_t ra = (size_t)(la & ((1 << lny) - 1)) * N, rb = ra + N;
+  const T* u_old = (const T*)u_old_f.at(f);
+  const T* d_old = (const T*)d_old_f.at(f);
+  T* u_out = (T*)u_out_f.at(f);
+  T* d_out = (T*)d_out_f.at(f);
+  T* prev_out = (T*)prev_out_f.at(f);
   cpx<T> u[G::R];
   if constexpr (MODE == SG_ENTRY) {
 #pragma unroll
     for (int s = 0; s < G::R; ++s) {
       const int e = t + s * G::TL;
       const T ua = va ? u_old[ra + e] : T(0), ub = vb ? u_old[rb + e] : T(0);
-      if (d_out != nullptr) {
+      if (d_out_f.base != nullptr || d_out_f.table != nullptr) {
         if (va) d_out[ra + e] = ua - d_old[ra + e];
         if (vb) d_out[rb + e] = ub - d_old[rb + e];
       }
@@ -230,18 +237,18 @@ __global__ __launch_bounds__(256) void k_sg_h_finish(int npairs, int ncols, cons
 
 // ----------------------------------------------------------- launchers ---
 template <typename T>
-static hipError_t row(int mode, int nx, int nlines, const void* W, const void* u_old, const void* d_old,
-                      double alpha, void* u_out, void* d_out, void* prev_out, void* U, void* S, const void* tw,
-                      hipStream_t s) {
+static hipError_t row(int mode, int nx, int nlines, int ny, const void* W, FieldRef u_old, FieldRef d_old,
+                      double alpha, FieldRef u_out, FieldRef d_out, FieldRef prev_out, void* U, void* S,
+                      const void* tw, hipStream_t s) {
   bool ok = dispatch_n(nx, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
     using G = RowGeom<T, N>;
     const int grid = ((nlines + 1) / 2 + G::LPB - 1) / G::LPB;
     auto go = [&](auto kern) {
       allow_lds(kern, G::LDS_BYTES);
-      hipLaunchKernelGGL(kern, dim3(grid), dim3(G::THREADS), G::LDS_BYTES, s, (const cpx<T>*)W, (const T*)u_old,
-                         (const T*)d_old, (T)alpha, (T*)u_out, (T*)d_out, (T*)prev_out, (cpx<T>*)U, (cpx<T>*)S,
-                         nlines, (const cpx<T>*)tw);
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(G::THREADS), G::LDS_BYTES, s, (const cpx<T>*)W, u_old, d_old,
+                         (T)alpha, u_out, d_out, prev_out, (cpx<T>*)U, (cpx<T>*)S, nlines, ilog2c(ny),
+                         (const cpx<T>*)tw);
     };
     if (mode == SG_ENTRY) go(k_sg_row<T, N, SG_ENTRY>);
     else if (mode == SG_STEP) go(k_sg_row<T, N, SG_STEP>);
@@ -250,11 +257,11 @@ static hipError_t row(int mode, int nx, int nlines, const void* W, const void* u
   return ok ? hipGetLastError() : hipErrorInvalidValue;
 }
 
-hipError_t sg_row(Prec p, int mode, int nx, int nlines, const void* W, const void* u_old, const void* d_old,
-                  double alpha, void* u_out, void* d_out, void* prev_out, void* U, void* S, const void* tw,
-                  hipStream_t s) {
-  return p == P32 ? row<float>(mode, nx, nlines, W, u_old, d_old, alpha, u_out, d_out, prev_out, U, S, tw, s)
-                  : row<double>(mode, nx, nlines, W, u_old, d_old, alpha, u_out, d_out, prev_out, U, S, tw, s);
+hipError_t sg_row(Prec p, int mode, int nx, int nlines, int ny, const void* W, FieldRef u_old, FieldRef d_old,
+                  double alpha, FieldRef u_out, FieldRef d_out, FieldRef prev_out, void* U, void* S,
+                  const void* tw, hipStream_t s) {
+  return p == P32 ? row<float>(mode, nx, nlines, ny, W, u_old, d_old, alpha, u_out, d_out, prev_out, U, S, tw, s)
+                  : row<double>(mode, nx, nlines, ny, W, u_old, d_old, alpha, u_out, d_out, prev_out, U, S, tw, s);
 }
 
 template <typename T>

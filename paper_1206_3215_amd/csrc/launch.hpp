@@ -10,6 +10,23 @@ namespace pst {
 
 enum Prec { P32 = 0, P64 = 1 };
 
+// Addressing of caller fields: field f starts at table[f] when a device
+// pointer table is given, else at base + f * stride bytes.  Used for every
+// field the solver entry points take from the caller, so that a launch can
+// advance simulations whose fields are not contiguous (batched requests).
+struct FieldRef {
+  char* base = nullptr;
+  long long stride = 0;
+  void* const* table = nullptr;
+  __host__ __device__ char* at(int f) const { return table ? (char*)table[f] : base + f * stride; }
+};
+inline FieldRef contiguous(const void* p, size_t field_bytes) {
+  FieldRef r;
+  r.base = (char*)p;
+  r.stride = (long long)field_bytes;
+  return r;
+}
+
 // Status bits latched by kernels into a plan's device status word.
 enum : int { ST_NONFINITE = 1, ST_NOT_CONVERGED = 2 };
 
@@ -31,18 +48,19 @@ hipError_t fft_col_c2c(Prec p, int ny, int ncols, int ld, int nfields, const voi
 // Real rows.  r2c: nlines real rows of length n -> half spectra (n/2+1).
 // c2r: half spectra -> real rows, times scale.  Rows are processed in
 // pairs; nlines may be odd.
-hipError_t fft_row_r2c(Prec p, int n, int nlines, const void* in, void* out, const void* tw,
+// The real side is a FieldRef of fields with ny rows (ny a power of two).
+hipError_t fft_row_r2c(Prec p, int n, int nlines, int ny, FieldRef in, void* out, const void* tw,
                        hipStream_t s);
-hipError_t fft_row_c2r(Prec p, int n, int nlines, const void* in, void* out, double scale,
+hipError_t fft_row_c2r(Prec p, int n, int nlines, int ny, const void* in, FieldRef out, double scale,
                        const void* tw, hipStream_t s);
 
 // ----------------------------------------------------------------- NLS ---
 // mode 0: H = nx * FFT_x(psi); 1: H <- FFT_x(e^{-i c |iFFT_x H|^2} iFFT_x H);
 // 2: psi = iFFT_x(H) / nx.  phase_coef = g dt / nx^2, scale as stated.
-hipError_t nls_row(Prec p, int nx, int nlines, void* psi, int mode, double phase_coef,
+hipError_t nls_row(Prec p, int nx, int nlines, int ny, FieldRef psi, int mode, double phase_coef,
                    double scale, const void* tw, hipStream_t s);
 // Column: FFT_y, multiply by (1 + ex[mx]) (1 + ey[my]) / (nx ny), iFFT_y (in place).
-hipError_t nls_col(Prec p, int ny, int nx, int nfields, void* psi, const void* tw,
+hipError_t nls_col(Prec p, int ny, int nx, int nfields, FieldRef psi, const void* tw,
                    const void* ex, const void* ey, int W, hipStream_t s);
 
 // ------------------------------------------------------- reductions ---
@@ -67,9 +85,9 @@ hipError_t nls_cq_finish(int nfields, int ny, int nx, const double* row_part,
 //   mode 2 (final): d = alpha d_old + C2R_x(W); u_out = u_old + d;
 //                   prev_out = u_old.
 // Each element is read before it is written, so outputs may alias inputs.
-hipError_t sg_row(Prec p, int mode, int nx, int nlines, const void* W, const void* u_old, const void* d_old,
-                  double alpha, void* u_out, void* d_out, void* prev_out, void* U, void* S, const void* tw,
-                  hipStream_t s);
+hipError_t sg_row(Prec p, int mode, int nx, int nlines, int ny, const void* W, FieldRef u_old, FieldRef d_old,
+                  double alpha, FieldRef u_out, FieldRef d_out, FieldRef prev_out, void* U, void* S,
+                  const void* tw, hipStream_t s);
 // Column pass: W = iFFT_y(c1m FFT_y(U) - c2 FFT_y(S)) with a = |k|^2 dt2q,
 // c1m = -2 cnum a/(1+a) sc, c2 = c2num/(1+a) sc.
 hipError_t sg_col(Prec p, int ny, int nx, int nfields, const void* U, const void* S, void* W, const void* tw,
@@ -105,10 +123,11 @@ hipError_t ns_row(Prec p, int nx, int nlines, int ny, const void* D, size_t dstr
 // Column pass, mode 0 entry / 1 first iteration / 2 later iteration / 3 exit.
 hipError_t ns_col(Prec p, int mode, int ny, int nfields, const NsPtrs& P, const NsScalars& S, const int* done,
                   const void* tw, int Wt, hipStream_t s);
-// Convergence bookkeeping per field (see k_ns_finish).
+// Convergence bookkeeping per field (see k_ns_finish); fstat, if not NULL,
+// holds a per-field pointer receiving that field's ST_ bits.
 hipError_t ns_finish(int nfields, int ncols, const double* part, double vol, double tol, double fp_floor,
                      int max_iter, int fixed, int first, int* done, int* iters, int* iters_out, double* resid,
-                     int* status, hipStream_t s);
+                     int* status, int* const* fstat, hipStream_t s);
 // Diagnostics from omega's x-transform XH: energy and enstrophy.
 hipError_t ns_cq_col(Prec p, int ny, int nx, int nfields, const void* XH, double* part, double kx0, double ky0,
                      const void* tw, int Wt, hipStream_t s);

@@ -302,7 +302,9 @@ pst_status fft2d_exec(pst_plan pl, const void* in, void* out, int sign) {
   }
   if (in == out) return fail(PST_ERR_INVALID, "R2C transforms cannot run in place");
   if (!inv) {
-    st = hip_check(fft_row_r2c(pl->P, nx, B * ny, in, out, pl->tw_x, pl->stream), "r2c row pass");
+    st = hip_check(fft_row_r2c(pl->P, nx, B * ny, ny, contiguous(in, (size_t)nx * ny * pl->rsize), out, pl->tw_x,
+                               pl->stream),
+                   "r2c row pass");
     if (st != PST_OK) return st;
     return hip_check(fft_col_c2c(pl->P, ny, h, h, B, out, out, false, 1.0, pl->tw_y, col_w(pl, ny), pl->stream),
                      "column pass");
@@ -312,7 +314,9 @@ pst_status fft2d_exec(pst_plan pl, const void* in, void* out, int sign) {
   st = hip_check(fft_col_c2c(pl->P, ny, h, h, B, in, tmp, true, 1.0, pl->tw_y, col_w(pl, ny), pl->stream),
                  "column pass");
   if (st != PST_OK) return st;
-  return hip_check(fft_row_c2r(pl->P, nx, B * ny, tmp, out, sc, pl->tw_x, pl->stream), "c2r row pass");
+  return hip_check(fft_row_c2r(pl->P, nx, B * ny, ny, tmp, contiguous(out, (size_t)nx * ny * pl->rsize), sc, pl->tw_x,
+                               pl->stream),
+                   "c2r row pass");
 }
 
 pst_status pst_profile_enable(pst_plan pl, int enable) {

@@ -4,6 +4,10 @@
 #include <cmath>
 #include <algorithm>
 #include <complex>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -59,14 +63,18 @@ pst_status need_kind(Plan* pl, pst_kind k, const char* who) {
 
 extern "C" {
 
-pst_status nls_step(pst_plan pl, void* psi, const pst_nls_params* p, int nsteps) {
+static pst_status nls_check(Plan* pl, const pst_nls_params* p, int nsteps) {
   TRY(need_kind(pl, PST_C2C, "nls_step"));
-  TRY(check_field(psi, "psi"));
   if (p == nullptr) return fail(PST_ERR_INVALID, "params is NULL");
   TRY(check_domain(p->d));
   if (!(p->dt != 0.0) || !std::isfinite(p->dt)) return fail(PST_ERR_INVALID, "dt must be finite and nonzero");
   if (!std::isfinite(p->g)) return fail(PST_ERR_INVALID, "g must be finite");
   if (nsteps < 0) return fail(PST_ERR_INVALID, "nsteps must be >= 0");
+  return PST_OK;
+}
+
+// nsteps Strang steps of the pl->batch fields addressed by psi.
+static pst_status nls_run(Plan* pl, FieldRef psi, const pst_nls_params* p, int nsteps) {
   if (nsteps == 0) return PST_OK;
   TRY(nls_tables(pl, p));
   const int nx = pl->nx, ny = pl->ny, B = pl->batch, W = pl->Wcol;
@@ -76,7 +84,7 @@ pst_status nls_step(pst_plan pl, void* psi, const pst_nls_params* p, int nsteps)
   hipStream_t s = pl->stream;
   auto row = [&](int mode, double pc_, double scale) {
     if (mode == 1) prof_begin(pl, PST_PASS_NLS_ROW);
-    pst_status r = hip_check(nls_row(pl->P, nx, lines, psi, mode, pc_, scale, pl->tw_x, s), "nls row");
+    pst_status r = hip_check(nls_row(pl->P, nx, lines, ny, psi, mode, pc_, scale, pl->tw_x, s), "nls row");
     if (mode == 1) prof_end(pl);
     return r;
   };
@@ -95,6 +103,12 @@ pst_status nls_step(pst_plan pl, void* psi, const pst_nls_params* p, int nsteps)
   TRY(row(1, pc, 1.0));
   TRY(col(t.ex_half, t.ey_half));
   return row(2, 0.0, 1.0 / nx);
+}
+
+pst_status nls_step(pst_plan pl, void* psi, const pst_nls_params* p, int nsteps) {
+  TRY(nls_check(pl, p, nsteps));
+  TRY(check_field(psi, "psi"));
+  return nls_run(pl, contiguous(psi, (size_t)pl->nx * pl->ny * pl->csize), p, nsteps);
 }
 
 pst_status conserved_quantities(pst_plan pl, pst_eq eq, const void* f0, const void* f1,
@@ -144,7 +158,8 @@ pst_status conserved_quantities(pst_plan pl, pst_eq eq, const void* f0, const vo
     const double n2 = (double)nx * ny;
     const double en = 0.5 * p->d.lx * p->d.ly / (n2 * n2);
     const double zz = 0.5 * (p->d.lx / nx) * (p->d.ly / ny) / n2;
-    TRY(hip_check(fft_row_r2c(pl->P, nx, B * ny, f0, XH, pl->tw_x, s), "NS cq row"));
+    TRY(hip_check(fft_row_r2c(pl->P, nx, B * ny, ny, contiguous(f0, (size_t)nx * ny * pl->rsize), XH, pl->tw_x, s),
+                  "NS cq row"));
     TRY(hip_check(ns_cq_col(pl->P, ny, nx, B, XH, colp, 2 * M_PI / p->d.lx, 2 * M_PI / p->d.ly, pl->tw_y, col_w(pl, ny), s),
                   "NS cq column"));
     TRY(hip_check(ns_cq_finish(B, h, colp, en, zz, pl->dres, pl->dstatus, s), "NS cq finish"));
@@ -177,27 +192,27 @@ pst_status sg_start(pst_plan pl, const void* u0, const void* v0, void* u_prev, v
   if (u_prev == u_curr) return fail(PST_ERR_INVALID, "sg_start: u_prev and u_curr must differ");
   if (u_curr == u0 || u_prev == v0) return fail(PST_ERR_INVALID, "sg_start: outputs alias the wrong inputs");
   const int nx = pl->nx, ny = pl->ny, B = pl->batch, lines = B * ny;
+  const size_t fb = (size_t)nx * ny * pl->rsize;
   void* U = ws_at(pl, pl->off_spec);
   void* S = ws_at(pl, pl->off_spec2);
   void* W = ws_at(pl, pl->off_spec3);
   const double sc = 0.5 / ((double)nx * ny), dt = p->dt;
   hipStream_t s = pl->stream;
-  TRY(hip_check(sg_row(pl->P, 0, nx, lines, nullptr, u0, nullptr, 0.0, nullptr, nullptr, nullptr, U, S, pl->tw_x, s),
+  const FieldRef none;
+  TRY(hip_check(sg_row(pl->P, 0, nx, lines, ny, nullptr, contiguous(u0, fb), none, 0.0, none, none, none, U, S,
+                       pl->tw_x, s),
                 "sg entry row"));
   // u^1 - u^0 = iFFT((c1s - 1) U - c2s S) + dt v0, c1s = (1-a)/(1+a), c2s = dt^2/(2(1+a))
   TRY(hip_check(sg_col(pl->P, ny, nx, B, U, S, W, pl->tw_y, 2 * M_PI / p->d.lx, 2 * M_PI / p->d.ly,
                        0.25 * dt * dt, 1.0, 0.5 * dt * dt, sc, col_w(pl, ny), s),
                 "sg start column"));
-  return hip_check(sg_row(pl->P, 2, nx, lines, W, u0, v0, dt, u_curr, nullptr, u_prev, nullptr, nullptr, pl->tw_x, s),
+  return hip_check(sg_row(pl->P, 2, nx, lines, ny, W, contiguous(u0, fb), contiguous(v0, fb), dt,
+                          contiguous(u_curr, fb), none, contiguous(u_prev, fb), nullptr, nullptr, pl->tw_x, s),
                    "sg start row");
 }
 
-pst_status sg_step(pst_plan pl, void* u_prev, void* u_curr, const pst_sg_params* p, int nsteps) {
-  TRY(sg_check(pl, p, "sg_step"));
-  TRY(check_field(u_prev, "u_prev"));
-  TRY(check_field(u_curr, "u_curr"));
-  if (u_prev == u_curr) return fail(PST_ERR_INVALID, "sg_step: u_prev and u_curr must differ");
-  if (nsteps < 0) return fail(PST_ERR_INVALID, "nsteps must be >= 0");
+// nsteps of the pl->batch field pairs (u_prev, u_curr).
+static pst_status sg_run(Plan* pl, FieldRef u_prev, FieldRef u_curr, const pst_sg_params* p, int nsteps) {
   if (nsteps == 0) return PST_OK;
   const int nx = pl->nx, ny = pl->ny, B = pl->batch, lines = B * ny;
   void* U = ws_at(pl, pl->off_spec);
@@ -207,6 +222,7 @@ pst_status sg_step(pst_plan pl, void* u_prev, void* u_curr, const pst_sg_params*
   const double kx0 = 2 * M_PI / p->d.lx, ky0 = 2 * M_PI / p->d.ly;
   const int Wt = col_w(pl, ny);
   hipStream_t s = pl->stream;
+  const FieldRef none;
   auto col = [&]() {
     prof_begin(pl, PST_PASS_SG_COL);
     pst_status r = hip_check(sg_col(pl->P, ny, nx, B, U, S, W, pl->tw_y, kx0, ky0, 0.25 * dt * dt, 2.0, dt * dt, sc,
@@ -216,25 +232,34 @@ pst_status sg_step(pst_plan pl, void* u_prev, void* u_curr, const pst_sg_params*
     return r;
   };
   // u_curr holds u^n; u_prev's buffer holds the increment d^n during the call
-  TRY(hip_check(sg_row(pl->P, 0, nx, lines, nullptr, u_curr, u_prev, 0.0, nullptr, u_prev, nullptr, U, S, pl->tw_x, s),
+  TRY(hip_check(sg_row(pl->P, 0, nx, lines, ny, nullptr, u_curr, u_prev, 0.0, none, u_prev, none, U, S, pl->tw_x, s),
                 "sg entry row"));
   TRY(col());
   for (int i = 0; i < nsteps - 1; ++i) {
     prof_begin(pl, PST_PASS_SG_ROW);
-    TRY(hip_check(sg_row(pl->P, 1, nx, lines, W, u_curr, u_prev, 1.0, u_curr, u_prev, nullptr, U, S, pl->tw_x, s),
+    TRY(hip_check(sg_row(pl->P, 1, nx, lines, ny, W, u_curr, u_prev, 1.0, u_curr, u_prev, none, U, S, pl->tw_x, s),
                   "sg row"));
     prof_end(pl);
     TRY(col());
   }
   // last step: u_curr <- u^N, u_prev <- u^{N-1} (the level it replaces)
-  return hip_check(sg_row(pl->P, 2, nx, lines, W, u_curr, u_prev, 1.0, u_curr, nullptr, u_prev, nullptr, nullptr,
+  return hip_check(sg_row(pl->P, 2, nx, lines, ny, W, u_curr, u_prev, 1.0, u_curr, none, u_prev, nullptr, nullptr,
                           pl->tw_x, s),
                    "sg final row");
 }
 
-pst_status ns_step(pst_plan pl, void* omega, const pst_ns_params* p, int nsteps, int* dev_iters) {
+pst_status sg_step(pst_plan pl, void* u_prev, void* u_curr, const pst_sg_params* p, int nsteps) {
+  TRY(sg_check(pl, p, "sg_step"));
+  TRY(check_field(u_prev, "u_prev"));
+  TRY(check_field(u_curr, "u_curr"));
+  if (u_prev == u_curr) return fail(PST_ERR_INVALID, "sg_step: u_prev and u_curr must differ");
+  if (nsteps < 0) return fail(PST_ERR_INVALID, "nsteps must be >= 0");
+  const size_t fb = (size_t)pl->nx * pl->ny * pl->rsize;
+  return sg_run(pl, contiguous(u_prev, fb), contiguous(u_curr, fb), p, nsteps);
+}
+
+static pst_status ns_check(Plan* pl, const pst_ns_params* p, int nsteps) {
   TRY(need_kind(pl, PST_R2C, "ns_step"));
-  TRY(check_field(omega, "omega"));
   if (p == nullptr) return fail(PST_ERR_INVALID, "params is NULL");
   TRY(check_domain(p->d));
   if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(PST_ERR_INVALID, "dt must be finite and > 0");
@@ -243,8 +268,13 @@ pst_status ns_step(pst_plan pl, void* omega, const pst_ns_params* p, int nsteps,
   if (p->max_iter < 1 || p->max_iter > 10000) return fail(PST_ERR_INVALID, "max_iter must be in [1, 10000]");
   if (p->fixed_iters < 0 || p->fixed_iters > 10000) return fail(PST_ERR_INVALID, "fixed_iters must be in [0, 10000]");
   if (nsteps < 0) return fail(PST_ERR_INVALID, "nsteps must be >= 0");
+  return ensure_workspace(pl);
+}
+
+// nsteps of the pl->batch vorticity fields addressed by omega.
+static pst_status ns_run(Plan* pl, FieldRef omega, const pst_ns_params* p, int nsteps, int* dev_iters,
+                         int* const* fstat = nullptr) {
   if (nsteps == 0) return PST_OK;
-  TRY(ensure_workspace(pl));
   const int nx = pl->nx, ny = pl->ny, B = pl->batch, lines = B * ny, h = nx / 2 + 1;
   const int Wt = col_w(pl, ny);
   hipStream_t s = pl->stream;
@@ -289,11 +319,11 @@ pst_status ns_step(pst_plan pl, void* omega, const pst_ns_params* p, int nsteps,
   };
   auto finish = [&](int first, int* iters_out) {
     return hip_check(ns_finish(B, h, P.part, vol, p->tol, fp_floor, p->max_iter, fixed, first, done, iters,
-                               iters_out, resid, pl->dstatus, s),
+                               iters_out, resid, pl->dstatus, fstat, s),
                      "ns finish");
   };
   // entry: w^n = rfft2(omega), increment 0, derivatives of w^n
-  TRY(hip_check(fft_row_r2c(pl->P, nx, lines, omega, (void*)P.NH, pl->tw_x, s), "ns entry row"));
+  TRY(hip_check(fft_row_r2c(pl->P, nx, lines, ny, omega, (void*)P.NH, pl->tw_x, s), "ns entry row"));
   TRY(col(0));
   std::vector<int> hbuf(2 * B);
   for (int step = 0; step < nsteps; ++step) {
@@ -330,11 +360,246 @@ pst_status ns_step(pst_plan pl, void* omega, const pst_ns_params* p, int nsteps,
   }
   // exit: omega = irfft2(w^n + d)
   TRY(col(3));
-  return hip_check(fft_row_c2r(pl->P, nx, lines, P.OUT, omega, 1.0 / ((double)nx * ny), pl->tw_x, s), "ns exit row");
+  return hip_check(fft_row_c2r(pl->P, nx, lines, ny, P.OUT, omega, 1.0 / ((double)nx * ny), pl->tw_x, s),
+                   "ns exit row");
 }
 
-pst_status solve_batch(const pst_request*, int, void*) {
-  return fail(PST_ERR_UNSUPPORTED, "solve_batch: not available yet");
+pst_status ns_step(pst_plan pl, void* omega, const pst_ns_params* p, int nsteps, int* dev_iters) {
+  TRY(ns_check(pl, p, nsteps));
+  TRY(check_field(omega, "omega"));
+  return ns_run(pl, contiguous(omega, (size_t)pl->nx * pl->ny * pl->rsize), p, nsteps, dev_iters);
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ batching ---
+// solve_batch groups requests that share (equation, nx, ny, precision,
+// parameters).  Each group runs on an internal plan whose capacity is the
+// next power of two of the group size; the callers' fields are reached
+// through device pointer tables, so nothing is gathered or copied.  Groups
+// are forked onto library-owned streams (default priority) and joined back
+// on the caller's stream, so size classes overlap on the device.  Requests
+// of one group with different step counts advance in chunks of the smallest
+// remaining count; a chunk's launch sequence is captured once into a
+// hipGraph and replayed when the same (plan, fields, chunk) comes back.
+namespace {
+
+struct GroupKey {
+  int eq, nx, ny, prec, cap;
+  hipStream_t stream;
+  bool operator<(const GroupKey& o) const {
+    return std::tie(eq, nx, ny, prec, cap, stream) < std::tie(o.eq, o.nx, o.ny, o.prec, o.cap, o.stream);
+  }
+};
+
+struct BatchPlan {
+  Plan* pl = nullptr;
+  void** dtab = nullptr;  // device: cap x {f0, f1, status slot}
+  int* dfst = nullptr;    // device: per-field status (NS)
+  std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
+};
+
+std::mutex g_batch_mu;
+std::map<GroupKey, BatchPlan> g_batch_plans;
+std::vector<hipStream_t> g_side_streams;
+
+size_t params_size(int eq) {
+  return eq == PST_NLS ? sizeof(pst_nls_params) : eq == PST_SG ? sizeof(pst_sg_params) : sizeof(pst_ns_params);
+}
+
+pst_status batch_plan(const pst_request& r, int cap, hipStream_t s, BatchPlan** out) {
+  GroupKey k{(int)r.eq, r.nx, r.ny, (int)r.prec, cap, s};
+  auto it = g_batch_plans.find(k);
+  if (it != g_batch_plans.end()) {
+    *out = &it->second;
+    return PST_OK;
+  }
+  BatchPlan bp;
+  TRY(fft2d_plan(r.nx, r.ny, r.eq == PST_NLS ? PST_C2C : PST_R2C, r.prec, cap, s, &bp.pl));
+  TRY(ensure_workspace(bp.pl));
+  void* p = nullptr;
+  TRY(hip_check(hipMalloc(&p, (size_t)cap * (4 * sizeof(void*) + sizeof(int)) + 256), "hipMalloc(tables)"));
+  bp.pl->owned.push_back(p);
+  bp.dtab = static_cast<void**>(p);
+  bp.dfst = reinterpret_cast<int*>(static_cast<char*>(p) + (size_t)cap * 4 * sizeof(void*));
+  auto res = g_batch_plans.emplace(k, bp);
+  *out = &res.first->second;
+  return PST_OK;
+}
+
+pst_status check_request(const pst_request& r, int i) {
+  if (r.eq != PST_NLS && r.eq != PST_SG && r.eq != PST_NS) return fail(PST_ERR_INVALID, "request %d: unknown equation", i);
+  if (r.nx < 4 || r.nx > 8192 || (r.nx & (r.nx - 1)) || r.ny < 4 || r.ny > 8192 || (r.ny & (r.ny - 1)))
+    return fail(PST_ERR_INVALID, "request %d: sizes must be powers of two in [4, 8192]", i);
+  if (r.prec != PST_FP32 && r.prec != PST_FP64) return fail(PST_ERR_INVALID, "request %d: unknown precision", i);
+  if (r.nsteps < 0) return fail(PST_ERR_INVALID, "request %d: nsteps < 0", i);
+  if (r.params == nullptr || r.f0 == nullptr || (r.eq == PST_SG && r.f1 == nullptr))
+    return fail(PST_ERR_INVALID, "request %d: NULL params or field", i);
+  if (r.eq == PST_SG && r.f0 == r.f1) return fail(PST_ERR_INVALID, "request %d: u_prev and u_curr must differ", i);
+  return PST_OK;
+}
+
+__global__ void k_scatter_status(const int* fst, int* const* dst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && dst[i] != nullptr) *dst[i] = (fst[i] & ST_NOT_CONVERGED) ? PST_ERR_NOT_CONVERGED : PST_OK;
+}
+
+}  // namespace
+
+// One chunk of a group: every field advances by k steps.
+static pst_status run_chunk(BatchPlan& bp, int eq, const void* params, int nf, int k, bool capture,
+                            const std::vector<uintptr_t>& key) {
+  Plan* pl = bp.pl;
+  const int cap = pl->batch;
+  pl->batch = nf;
+  FieldRef f0, f1;
+  f0.table = bp.dtab;
+  f1.table = bp.dtab + cap;
+  pst_status st = PST_OK;
+  int* const* fst = reinterpret_cast<int* const*>(bp.dtab + 2 * cap);
+  // tables are uploaded before any capture (a synchronous copy may not be captured)
+  if (eq == PST_NLS) TRY(nls_tables(pl, static_cast<const pst_nls_params*>(params)));
+  auto launch = [&]() -> pst_status {
+    if (eq == PST_NLS) return nls_run(pl, f0, static_cast<const pst_nls_params*>(params), k);
+    if (eq == PST_SG) return sg_run(pl, f0, f1, static_cast<const pst_sg_params*>(params), k);
+    return ns_run(pl, f0, static_cast<const pst_ns_params*>(params), k, nullptr, fst);
+  };
+  if (!capture) {
+    st = launch();
+  } else {
+    auto g = bp.graphs.find(key);
+    if (g == bp.graphs.end()) {
+      hipGraph_t graph;
+      st = hip_check(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+      if (st == PST_OK) {
+        pst_status ls = launch();
+        hipError_t e = hipStreamEndCapture(pl->stream, &graph);
+        st = ls != PST_OK ? ls : hip_check(e, "end capture");
+        if (st == PST_OK) {
+          hipGraphExec_t ex;
+          st = hip_check(hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0), "graph instantiate");
+          hipGraphDestroy(graph);
+          if (st == PST_OK) g = bp.graphs.emplace(key, ex).first;
+        }
+      }
+    }
+    if (st == PST_OK) st = hip_check(hipGraphLaunch(g->second, pl->stream), "graph launch");
+  }
+  pl->batch = cap;
+  return st;
+}
+
+extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stream) {
+  if (n < 0 || (n > 0 && reqs == nullptr)) return fail(PST_ERR_INVALID, "solve_batch: bad request array");
+  for (int i = 0; i < n; ++i) TRY(check_request(reqs[i], i));
+  std::lock_guard<std::mutex> lock(g_batch_mu);
+  hipStream_t caller = reinterpret_cast<hipStream_t>(hip_stream);
+  // group by (eq, nx, ny, prec, parameter bytes)
+  std::vector<std::vector<int>> groups;
+  std::map<std::vector<unsigned char>, int> gidx;
+  for (int i = 0; i < n; ++i) {
+    const pst_request& r = reqs[i];
+    std::vector<unsigned char> key(5 * sizeof(int) + params_size(r.eq));
+    int hdr[5] = {(int)r.eq, r.nx, r.ny, (int)r.prec, 0};
+    memcpy(key.data(), hdr, sizeof hdr);
+    memcpy(key.data() + sizeof hdr, r.params, params_size(r.eq));
+    auto it = gidx.find(key);
+    if (it == gidx.end()) {
+      gidx.emplace(key, (int)groups.size());
+      groups.push_back({i});
+    } else {
+      groups[it->second].push_back(i);
+    }
+  }
+  while (g_side_streams.size() < groups.size()) {
+    hipStream_t st;
+    TRY(hip_check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate"));
+    g_side_streams.push_back(st);
+  }
+  hipEvent_t fork;
+  TRY(hip_check(hipEventCreateWithFlags(&fork, hipEventDisableTiming), "hipEventCreate"));
+  TRY(hip_check(hipEventRecord(fork, caller), "hipEventRecord"));
+  std::vector<hipEvent_t> joins;
+  pst_status result = PST_OK;
+  for (size_t gi = 0; gi < groups.size() && result == PST_OK; ++gi) {
+    const std::vector<int>& g = groups[gi];
+    const pst_request& r0 = reqs[g[0]];
+    hipStream_t s = g_side_streams[gi];
+    result = hip_check(hipStreamWaitEvent(s, fork, 0), "hipStreamWaitEvent");
+    if (result != PST_OK) break;
+    // validate the shared parameters through the single-plan checks
+    int cap = 1;
+    while (cap < (int)g.size()) cap <<= 1;
+    BatchPlan* bp = nullptr;
+    if ((result = batch_plan(r0, cap, s, &bp)) != PST_OK) break;
+    Plan* pl = bp->pl;
+    if (r0.eq == PST_NLS) result = nls_check(pl, static_cast<const pst_nls_params*>(r0.params), 0);
+    else if (r0.eq == PST_SG) result = sg_check(pl, static_cast<const pst_sg_params*>(r0.params), "solve_batch");
+    else result = ns_check(pl, static_cast<const pst_ns_params*>(r0.params), 0);
+    if (result != PST_OK) break;
+    const bool fixed = r0.eq != PST_NS || static_cast<const pst_ns_params*>(r0.params)->fixed_iters > 0;
+    std::vector<int> left(g.size());
+    for (size_t j = 0; j < g.size(); ++j) left[j] = reqs[g[j]].nsteps;
+    if (r0.eq == PST_NS) result = hip_check(hipMemsetAsync(bp->dfst, 0, cap * sizeof(int), s), "clear status");
+    while (result == PST_OK) {
+      std::vector<int> act;
+      int k = 0;
+      for (size_t j = 0; j < g.size(); ++j)
+        if (left[j] > 0) {
+          act.push_back((int)j);
+          k = k == 0 ? left[j] : std::min(k, left[j]);
+        }
+      if (act.empty()) break;
+      std::vector<void*> tab(3 * cap, nullptr);
+      std::vector<uintptr_t> key;
+      for (size_t a = 0; a < act.size(); ++a) {
+        const pst_request& r = reqs[g[act[a]]];
+        tab[a] = r.f0;
+        tab[cap + a] = r.f1;
+        tab[2 * cap + a] = bp->dfst + act[a];
+        key.push_back((uintptr_t)r.f0);
+        key.push_back((uintptr_t)r.f1);
+      }
+      key.push_back((uintptr_t)k);
+      result = hip_check(hipMemcpyAsync(bp->dtab, tab.data(), tab.size() * sizeof(void*), hipMemcpyHostToDevice, s),
+                         "upload field table");
+      if (result != PST_OK) break;
+      result = run_chunk(*bp, r0.eq, r0.params, (int)act.size(), k, fixed, key);
+      for (int a : act) left[a] -= k;
+    }
+    if (result != PST_OK) break;
+    // per-request device status
+    std::vector<int*> stp(g.size());
+    bool any = false;
+    for (size_t j = 0; j < g.size(); ++j) {
+      stp[j] = reqs[g[j]].dev_status;
+      any = any || stp[j] != nullptr;
+    }
+    if (any) {
+      if (r0.eq != PST_NS) result = hip_check(hipMemsetAsync(bp->dfst, 0, cap * sizeof(int), s), "clear status");
+      int** dst = reinterpret_cast<int**>(bp->dtab + 3 * cap);
+      if (result == PST_OK)
+        result = hip_check(hipMemcpyAsync(dst, stp.data(), g.size() * sizeof(int*), hipMemcpyHostToDevice, s),
+                           "upload status table");
+      if (result == PST_OK) {
+        hipLaunchKernelGGL(k_scatter_status, dim3(((int)g.size() + 255) / 256), dim3(256), 0, s, bp->dfst, dst,
+                           (int)g.size());
+        result = hip_check(hipGetLastError(), "status scatter");
+      }
+    }
+    hipEvent_t j;
+    if (result == PST_OK) result = hip_check(hipEventCreateWithFlags(&j, hipEventDisableTiming), "hipEventCreate");
+    if (result == PST_OK) {
+      hipEventRecord(j, s);
+      joins.push_back(j);
+    }
+  }
+  for (hipEvent_t j : joins) {
+    hipStreamWaitEvent(caller, j, 0);
+    hipEventDestroy(j);
+  }
+  hipEventDestroy(fork);
+  return result;
+}
+
+

@@ -1,0 +1,122 @@
+"""solve_batch: mixed equations and uneven sizes in one call vs the single-plan path."""
+import numpy as np
+import pytest
+
+from paper_1206_3215_amd import inputs
+from tests.gpuutil import need_gpu, rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+D_NLS, D_SG, D_NS = inputs.PAPER_DOMAIN, inputs.PAPER_DOMAIN, inputs.NS_DOMAIN
+
+
+def single(eq, f0, f1, prm, nsteps, prec):
+    torch = need_gpu()
+    from paper_1206_3215_amd import binding as b
+    ny, nx = f0.shape
+    kind = b.PST_C2C if eq == "nls" else b.PST_R2C
+    plan = b.Plan(nx, ny, kind, prec, 1)
+    dt = plan.complex_dtype if eq == "nls" else plan.real_dtype
+    a = to_dev(f0[None], torch, dt)
+    if eq == "nls":
+        plan.nls_step(a, D_NLS, prm["dt"], 1.0, nsteps)
+        return to_host(a)[0], None
+    if eq == "sg":
+        bb = to_dev(f1[None], torch, dt)
+        plan.sg_step(a, bb, D_SG, prm["dt"], nsteps)
+        return to_host(a)[0], to_host(bb)[0]
+    plan.ns_step(a, D_NS, prm["dt"], prm["nu"], nsteps, tol=prm.get("tol", 1e-10),
+                 max_iter=prm.get("max_iter", 50), fixed_iters=prm.get("fixed", 0))
+    return to_host(a)[0], None
+
+
+def build_mix(prec):
+    rng = np.random.default_rng(0)
+    mix = []
+    for i, (n, steps) in enumerate([(64, 7), (64, 7), (64, 3), (128, 5)]):
+        mix.append(("nls", inputs.nls_gaussian(n, n, D_NLS, seed=i), None, {"dt": 1e-3}, steps))
+    for i, (nx, ny) in enumerate([(32, 64), (32, 64), (128, 128)]):
+        u0, _ = inputs.sg_gaussian(nx, ny, D_SG, seed=i)
+        mix.append(("sg", u0 - 0.01 * rng.standard_normal(u0.shape), u0, {"dt": 0.01}, 6))
+    for i, n in enumerate([64, 64, 128]):
+        mix.append(("ns", inputs.ns_random_phase(n, seed=i), None, {"dt": 1e-3, "nu": 1e-3, "fixed": 2}, 4))
+    mix.append(("ns", inputs.ns_random_phase(64, seed=9), None, {"dt": 1e-3, "nu": 1e-3}, 3))
+    return mix
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_mixed_batch_matches_single_runs(prec):
+    torch = need_gpu()
+    from paper_1206_3215_amd import binding as b
+    mix = build_mix(prec)
+    reqs, tens = [], []
+    for eq, f0, f1, prm, steps in mix:
+        cdt = (torch.complex128 if prec else torch.complex64) if eq == "nls" else (torch.float64 if prec else torch.float32)
+        a = to_dev(f0, torch, cdt)
+        bb = to_dev(f1, torch, cdt) if f1 is not None else None
+        d = {"nls": D_NLS, "sg": D_SG, "ns": D_NS}[eq]
+        pr = b.make_params(eq, d, prm["dt"], nu=prm.get("nu", 0.0), fixed_iters=prm.get("fixed", 0))
+        reqs.append({"eq": eq, "f0": a, "f1": bb, "params": pr, "nsteps": steps,
+                     "dev_status": torch.full((1,), -1, dtype=torch.int32, device="cuda")})
+        tens.append((a, bb))
+    b.solve_batch(reqs)
+    torch.cuda.synchronize()
+    tol = 1e-11 if prec else 1e-4
+    for (eq, f0, f1, prm, steps), (a, bb), r in zip(mix, tens, reqs):
+        ref0, ref1 = single(eq, f0, f1, prm, steps, prec)
+        assert rel_err(to_host(a), ref0) < tol, (eq, f0.shape, steps)
+        if ref1 is not None:
+            assert rel_err(to_host(bb), ref1) < tol
+        assert int(r["dev_status"].item()) == 0
+
+
+def test_uneven_ns_batch_bitwise_vs_alone():
+    # 4 x 1024^2 + 4 x 2048^2 vorticity fields, fixed iterations, FP32
+    torch = need_gpu()
+    from paper_1206_3215_amd import binding as b
+    fields = [inputs.ns_random_phase(1024 if s < 4 else 2048, seed=s) for s in range(8)]
+    pr = b.make_params("ns", D_NS, 1e-3, nu=1e-3, fixed_iters=2)
+    ts = [to_dev(f, torch, torch.float32) for f in fields]
+    b.solve_batch([{"eq": "ns", "f0": t, "params": pr, "nsteps": 3} for t in ts])
+    alone = to_dev(fields[5], torch, torch.float32)
+    b.solve_batch([{"eq": "ns", "f0": alone, "params": pr, "nsteps": 3}])
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(alone), to_host(ts[5]))
+    ref, _ = single("ns", fields[1], None, {"dt": 1e-3, "nu": 1e-3, "fixed": 2}, 3, 0)
+    assert np.array_equal(to_host(ts[1]), ref)
+
+
+def test_repeat_call_replays_graph_and_matches_double_steps():
+    torch = need_gpu()
+    from paper_1206_3215_amd import binding as b
+    f = [inputs.nls_gaussian(128, 128, D_NLS, seed=s) for s in range(3)]
+    ts = [to_dev(x, torch, torch.complex128) for x in f]
+    pr = b.make_params("nls", D_NLS, 1e-3)
+    for _ in range(3):
+        b.solve_batch([{"eq": "nls", "f0": t, "params": pr, "nsteps": 5} for t in ts])
+    torch.cuda.synchronize()
+    plan = b.Plan(128, 128, b.PST_C2C, b.PST_FP64, 1)
+    a = to_dev(f[2][None], torch, torch.complex128)
+    for _ in range(3):
+        plan.nls_step(a, D_NLS, 1e-3, 1.0, 5)
+    assert np.array_equal(to_host(a)[0], to_host(ts[2]))
+
+
+def test_not_converged_status_is_per_request():
+    torch = need_gpu()
+    from paper_1206_3215_amd import binding as b
+    good = b.make_params("ns", D_NS, 1e-3, nu=1e-3, tol=1e-10, max_iter=50)
+    bad = b.make_params("ns", D_NS, 1e-3, nu=1e-3, tol=0.0, max_iter=2)
+    ts = [to_dev(inputs.ns_random_phase(32, seed=s), torch, torch.float64) for s in range(2)]
+    st = [torch.full((1,), -1, dtype=torch.int32, device="cuda") for _ in range(2)]
+    b.solve_batch([{"eq": "ns", "f0": ts[0], "params": good, "nsteps": 2, "dev_status": st[0]},
+                   {"eq": "ns", "f0": ts[1], "params": bad, "nsteps": 2, "dev_status": st[1]}])
+    torch.cuda.synchronize()
+    assert int(st[0].item()) == b.PST_OK and int(st[1].item()) == b.PST_ERR_NOT_CONVERGED
+
+
+def test_invalid_requests_rejected_on_host():
+    torch = need_gpu()
+    from paper_1206_3215_amd import binding as b
+    t = to_dev(np.zeros((48, 48)), torch, torch.float32)
+    with pytest.raises(b.PstError):
+        b.solve_batch([{"eq": "ns", "f0": t, "params": b.make_params("ns", D_NS, 1e-3), "nsteps": 1}])
