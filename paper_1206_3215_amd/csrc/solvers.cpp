@@ -407,12 +407,20 @@ size_t params_size(int eq) {
   return eq == PST_NLS ? sizeof(pst_nls_params) : eq == PST_SG ? sizeof(pst_sg_params) : sizeof(pst_ns_params);
 }
 
+// One cached plan per (equation, size, precision, stream); a larger group
+// replaces it with a plan of the next power-of-two capacity, so the cache
+// holds at most one workspace per size class.
 pst_status batch_plan(const pst_request& r, int cap, hipStream_t s, BatchPlan** out) {
-  GroupKey k{(int)r.eq, r.nx, r.ny, (int)r.prec, cap, s};
+  GroupKey k{(int)r.eq, r.nx, r.ny, (int)r.prec, 0, s};
   auto it = g_batch_plans.find(k);
   if (it != g_batch_plans.end()) {
-    *out = &it->second;
-    return PST_OK;
+    if (it->second.pl->batch >= cap) {
+      *out = &it->second;
+      return PST_OK;
+    }
+    for (auto& g : it->second.graphs) hipGraphExecDestroy(g.second);
+    fft2d_destroy(it->second.pl);
+    g_batch_plans.erase(it);
   }
   BatchPlan bp;
   TRY(fft2d_plan(r.nx, r.ny, r.eq == PST_NLS ? PST_C2C : PST_R2C, r.prec, cap, s, &bp.pl));
@@ -533,6 +541,7 @@ extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stre
     BatchPlan* bp = nullptr;
     if ((result = batch_plan(r0, cap, s, &bp)) != PST_OK) break;
     Plan* pl = bp->pl;
+    cap = pl->batch;
     if (r0.eq == PST_NLS) result = nls_check(pl, static_cast<const pst_nls_params*>(r0.params), 0);
     else if (r0.eq == PST_SG) result = sg_check(pl, static_cast<const pst_sg_params*>(r0.params), "solve_batch");
     else result = ns_check(pl, static_cast<const pst_ns_params*>(r0.params), 0);
@@ -561,6 +570,7 @@ extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stre
         key.push_back((uintptr_t)r.f1);
       }
       key.push_back((uintptr_t)k);
+      key.push_back((uintptr_t)act.size());
       result = hip_check(hipMemcpyAsync(bp->dtab, tab.data(), tab.size() * sizeof(void*), hipMemcpyHostToDevice, s),
                          "upload field table");
       if (result != PST_OK) break;

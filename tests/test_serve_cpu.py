@@ -1,0 +1,114 @@
+"""Continuous-batching request loop, driven on the CPU by an executor that
+runs the oracle on tiny grids (same interface as the GPU executor)."""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import nls as onls, ns as ons, sg as osg
+from paper_1206_3215_amd import inputs
+from paper_1206_3215_amd.serve import BYTES_PER_POINT, Server, ServeParams, initial_condition
+
+P = ServeParams()
+D = inputs.PAPER_DOMAIN
+
+
+def solo(req):
+    """Oracle result of a request run alone in one go."""
+    ic = initial_condition(req)
+    if req.eq == "nls":
+        return onls.run(ic[0], D.lx, D.ly, P.nls_dt, 1.0, req.steps)[0]
+    if req.eq == "sg":
+        u1 = osg.start(ic[0], ic[1], D.lx, D.ly, P.sg_dt)
+        return osg.run(ic[0], u1, D.lx, D.ly, P.sg_dt, req.steps - 1)[1]
+    return ons.run(ic[0], 1.0, 1.0, P.ns_dt, P.ns_nu, req.steps, tol=P.ns_tol, max_iter=P.ns_max_iter)[0]
+
+
+class OracleExecutor:
+    def __init__(self, delay=0.0, fail_rid=None):
+        self.delay = delay
+        self.fail_rid = fail_rid
+        self.in_use = 0
+        self.peak = 0
+        self.calls = []
+
+    def footprint(self, req):
+        return BYTES_PER_POINT[req.eq] * req.n * req.n
+
+    def admit(self, req):
+        self.in_use += self.footprint(req)
+        self.peak = max(self.peak, self.in_use)
+        return {"req": req, "ic": initial_condition(req), "f": None, "g": None, "started": False}
+
+    def advance(self, work):
+        self.calls.append([w[0]["req"].rid for w in work])
+        time.sleep(self.delay)
+        for st, k in work:
+            r = st["req"]
+            if r.eq == "nls":
+                f = st["f"] if st["f"] is not None else st["ic"][0]
+                st["f"] = onls.run(f, D.lx, D.ly, P.nls_dt, 1.0, k)[0]
+            elif r.eq == "sg":
+                if not st["started"]:
+                    st["f"], st["g"] = st["ic"][0], osg.start(st["ic"][0], st["ic"][1], D.lx, D.ly, P.sg_dt)
+                    st["started"] = True
+                    k -= 1
+                st["f"], st["g"] = osg.run(st["f"], st["g"], D.lx, D.ly, P.sg_dt, k)
+            else:
+                f = st["f"] if st["f"] is not None else st["ic"][0]
+                st["f"] = ons.run(f, 1.0, 1.0, P.ns_dt, P.ns_nu, k, tol=P.ns_tol, max_iter=P.ns_max_iter)[0]
+
+    def fetch(self, st):
+        r = st["req"]
+        out = st["g"] if r.eq == "sg" else st["f"]
+        return out, (6 if r.rid == self.fail_rid else 0)
+
+    def release(self, st):
+        self.in_use -= self.footprint(st["req"])
+
+
+def small_mix(count=12, rate=200.0):
+    return inputs.serving_mix(count, rate_hz=rate, seed=7, log2n_range=(4, 5), steps_range=(3, 11))
+
+
+def test_results_equal_solo_runs():
+    reqs = small_mix()
+    rep = Server(OracleExecutor(), budget_bytes=10 ** 9, chunk=4).run(reqs, realtime=False)
+    assert [j.req.rid for j in rep.jobs] == [r.rid for r in reqs]
+    for j in rep.jobs:
+        np.testing.assert_array_equal(j.result, solo(j.req))
+    s = rep.summary()
+    assert s["requests"] == len(reqs) and s["p99_latency_s"] >= s["p50_latency_s"] > 0
+
+
+def test_budget_bounds_resident_footprint():
+    reqs = small_mix(16)
+    ex = OracleExecutor()
+    budget = 3 * BYTES_PER_POINT["sg"] * 32 * 32
+    rep = Server(ex, budget_bytes=budget, chunk=3).run(reqs, realtime=False)
+    assert len(rep.jobs) == 16 and ex.peak <= budget and ex.in_use == 0
+
+
+def test_continuous_admission_joins_running_batch():
+    # a late arrival is admitted while the first request is still running
+    reqs = [inputs.Request(0, "nls", 16, 40, 0.0), inputs.Request(1, "ns", 16, 4, 0.03)]
+    ex = OracleExecutor(delay=0.01)
+    rep = Server(ex, budget_bytes=10 ** 9, chunk=2).run(reqs, realtime=True)
+    j0, j1 = rep.jobs
+    assert j1.t_admit < j0.t_done
+    assert any(set(c) == {0, 1} for c in ex.calls)      # shared chunks
+    for j in rep.jobs:
+        np.testing.assert_array_equal(j.result, solo(j.req))
+
+
+def test_failure_is_isolated():
+    reqs = small_mix(6)
+    rep = Server(OracleExecutor(fail_rid=2), budget_bytes=10 ** 9, chunk=5).run(reqs, realtime=False)
+    for j in rep.jobs:
+        assert j.status == (6 if j.req.rid == 2 else 0)
+        np.testing.assert_array_equal(j.result, solo(j.req))
+
+
+def test_request_larger_than_budget_rejected():
+    with pytest.raises(ValueError):
+        Server(OracleExecutor(), budget_bytes=100).run([inputs.Request(0, "nls", 16, 3, 0.0)])
