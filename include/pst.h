@@ -203,6 +203,19 @@ const char* pst_last_error(void);
 /* Library version string. */
 const char* pst_version(void);
 
+/* Autotuning (not in the paper, which notes that launch parameters chosen
+ * by the compiler ran 2x slower and that autotuning would help): times the
+ * column pass of equation eq on this plan with each compiled column tile
+ * width (columns per block) on workspace data, keeps the fastest in the plan
+ * and remembers it for later plans of the same (eq, precision, nx, ny) in
+ * this process.  Synchronises.  *chosen (may be NULL) receives the width. */
+pst_status pst_autotune(pst_plan plan, pst_eq eq, int* chosen);
+
+/* Column tile (columns per block) used by this plan's column passes.  w must
+ * be one of the widths compiled for length ny (the widest that fits the
+ * block and LDS limits, or half of it); otherwise PST_ERR_INVALID. */
+pst_status pst_set_column_tile(pst_plan plan, int w);
+
 /* Per-pass timing.  While enabled, every pass kernel that plan launches is
  * bracketed by a pair of HIP events recorded on the plan's stream.
  * pst_profile_read synchronises the stream and returns, for pass id

@@ -68,6 +68,8 @@ _SIGS = {
     "conserved_quantities": [_vp, C.c_int, _vp, _vp, _vp, C.POINTER(C.c_double)],
     "pst_sync_status": [_vp, C.POINTER(C.c_int)],
     "solve_batch": [C.POINTER(Request), C.c_int, _vp],
+    "pst_autotune": [_vp, C.c_int, C.POINTER(C.c_int)],
+    "pst_set_column_tile": [_vp, C.c_int],
     "pst_profile_enable": [_vp, C.c_int],
     "pst_profile_read": [_vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)],
     "pst_last_error": [],
@@ -178,6 +180,15 @@ class Plan:
                                       out.ctypes.data_as(C.POINTER(C.c_double)))
         check(st, "conserved_quantities")
         return out.reshape(self.batch, 4)
+
+    def autotune(self, eq: str) -> int:
+        """Pick the fastest compiled column tile for this plan; returns it."""
+        w = C.c_int()
+        check(lib.pst_autotune(self.handle, EQ[eq], C.byref(w)), "pst_autotune")
+        return w.value
+
+    def set_column_tile(self, w: int) -> None:
+        check(lib.pst_set_column_tile(self.handle, int(w)), "pst_set_column_tile")
 
     def profile_enable(self, on: bool = True) -> None:
         check(lib.pst_profile_enable(self.handle, int(on)), "pst_profile_enable")

@@ -54,9 +54,11 @@ __host__ __device__ constexpr int twiddle_table_len(int N) {
   return stage_tw_offset(N, line_radix(N), num_stages(N, line_radix(N)));
 }
 
-// LDS slots of one line: one pad slot every 16 elements against bank conflicts.
-__host__ __device__ constexpr int lds_line_len(int N) { return N + N / 16 + 1; }
-__device__ __forceinline__ int lds_idx(int e) { return e + (e >> 4); }
+// LDS slot of element e of a line: one pad slot every 16 elements.  A
+// column tile interleaves its WS lines (slot * WS + line), so the lanes of a
+// wave, which run over adjacent lines first, touch adjacent slots.
+__host__ __device__ constexpr int lds_line_len(int N) { return N + N / 16; }
+__host__ __device__ __forceinline__ int lds_idx(int e) { return e + (e >> 4); }
 
 // ----------------------------------------------------------- butterflies ---
 // Multiply by exp(-+ 2 pi i m / 16) with compile-time m; INV selects +.
@@ -198,11 +200,18 @@ __host__ __device__ __forceinline__ void dft(cpx<T>* v) {
 }
 
 // ------------------------------------------------------------ line FFT ---
+// LDS addressing with one base per butterfly and compile-time offsets: for
+// every stage shape used here (Ns a power of two; Ns >= 16, or base mod 16 <
+// Ns with q*Ns mod 16 <= 16 - Ns, or Ns = 1 with base a multiple of the
+// radix), lds_idx(base + q*Ns) = lds_idx(base) + q*Ns + ((q*Ns) >> 4), and
+// lds_idx(t + s*TL) = lds_idx(t) + s*TL + ((s*TL) >> 4) for t < TL.
+__host__ __device__ constexpr int lds_off(int x) { return x + (x >> 4); }
+
 // One Stockham stage for thread t; outputs either stay in registers (last
 // stage) or are scattered to the line's LDS buffer.
-template <int N, int S, bool INV, typename T>
-__device__ __forceinline__ void line_stage(cpx<T> (&v)[line_radix(N)], cpx<T>* lds, int t,
-                                           const cpx<T>* __restrict__ tw) {
+template <int N, int S, bool INV, int WS, typename T>
+__host__ __device__ __forceinline__ void line_stage(cpx<T> (&v)[line_radix(N)], cpx<T>* lds, int t,
+                                                    const cpx<T>* __restrict__ tw) {
   constexpr int R = line_radix(N);
   constexpr int TL = N / R;
   constexpr int r = stage_radix(N, R, S);
@@ -217,10 +226,11 @@ __device__ __forceinline__ void line_stage(cpx<T> (&v)[line_radix(N)], cpx<T>* l
 #pragma unroll
     for (int q = 0; q < r; ++q) w[q] = v[b + q * B];
     if constexpr (Ns > 1) {
-      const int k = j & (Ns - 1);
+      const unsigned k = (unsigned)j & (Ns - 1);
 #pragma unroll
       for (int q = 1; q < r; ++q) {
-        const cpx<T> c = tw[toff + (q - 1) * Ns + k];
+        const cpx<T>* twq = tw + (toff + (q - 1) * Ns);  // uniform base, per-lane offset k
+        const cpx<T> c = twq[k];
         w[q] = INV ? cmul_conj(w[q], c) : cmul(w[q], c);
       }
     }
@@ -229,36 +239,45 @@ __device__ __forceinline__ void line_stage(cpx<T> (&v)[line_radix(N)], cpx<T>* l
 #pragma unroll
       for (int q = 0; q < r; ++q) v[b + q * B] = w[q];
     } else {
-      const int base = (j / Ns) * Ns * r + (j & (Ns - 1));
+      const int base = ((j / Ns) * Ns * r) + (j & (Ns - 1));
+      cpx<T>* pw = lds + lds_idx(base) * WS;
 #pragma unroll
-      for (int q = 0; q < r; ++q) lds[lds_idx(base + q * Ns)] = w[q];
+      for (int q = 0; q < r; ++q) pw[lds_off(q * Ns) * WS] = w[q];
     }
   }
 }
 
-template <int N, int S, bool INV, typename T>
-__device__ __forceinline__ void line_stages(cpx<T> (&v)[line_radix(N)], cpx<T>* lds, int t,
-                                            const cpx<T>* __restrict__ tw) {
+template <int N, int S, bool INV, int WS, typename T>
+__host__ __device__ __forceinline__ void line_read(cpx<T> (&v)[line_radix(N)], const cpx<T>* lds, int t) {
   constexpr int R = line_radix(N);
   constexpr int TL = N / R;
-  if constexpr (S < num_stages(N, R)) {
-    line_stage<N, S, INV>(v, lds, t, tw);
-    if constexpr (S < num_stages(N, R) - 1) {
-      __syncthreads();
+  const cpx<T>* pr = lds + lds_idx(t) * WS;
 #pragma unroll
-      for (int s = 0; s < R; ++s) v[s] = lds[lds_idx(t + s * TL)];
+  for (int s = 0; s < R; ++s) v[s] = pr[lds_off(s * TL) * WS];
+}
+
+template <int N, int S, bool INV, int WS, typename T>
+__device__ __forceinline__ void line_stages(cpx<T> (&v)[line_radix(N)], cpx<T>* lds, int t,
+                                            const cpx<T>* __restrict__ tw) {
+  if constexpr (S < num_stages(N, line_radix(N))) {
+    line_stage<N, S, INV, WS>(v, lds, t, tw);
+    if constexpr (S < num_stages(N, line_radix(N)) - 1) {
       __syncthreads();
-      line_stages<N, S + 1, INV>(v, lds, t, tw);
+      line_read<N, S, INV, WS>(v, lds, t);
+      __syncthreads();
+      line_stages<N, S + 1, INV, WS>(v, lds, t, tw);
     }
   }
 }
 
 // Full unnormalised FFT of a line whose N/R owners all call this together
 // (every thread of the block must call it: it contains block barriers).
-template <int N, bool INV, typename T>
+// lds points at the line's first slot; WS is the slot stride (lines per
+// interleaved tile).
+template <int N, bool INV, int WS = 1, typename T>
 __device__ __forceinline__ void line_fft(cpx<T> (&v)[line_radix(N)], cpx<T>* lds, int t,
                                          const cpx<T>* __restrict__ tw) {
-  line_stages<N, 0, INV>(v, lds, t, tw);
+  line_stages<N, 0, INV, WS>(v, lds, t, tw);
 }
 
 }  // namespace pst

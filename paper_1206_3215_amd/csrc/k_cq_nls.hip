@@ -41,26 +41,25 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_nls_cq_row(
   }
 }
 
-template <typename T, int N>
-__global__ __launch_bounds__(1024) void k_nls_cq_col(cpx<T>* spec, int nx, int tiles_per_field,
+template <typename T, int N, int WT>
+__global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_nls_cq_col(cpx<T>* spec, int nx, int tiles_per_field,
                                                      double* part, const cpx<T>* __restrict__ tw,
                                                      double kx0, double ky0) {
-  using G = ColGeom<T, N>;
+  using G = ColGeom<T, N, WT>;
   extern __shared__ char smem[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
   __shared__ double red[1024];
-  const int W = blockDim.x / G::TL;
-  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  const int c = threadIdx.x % WT, t = threadIdx.x / WT;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int field = tile / tiles_per_field;
-  const int col = (tile % tiles_per_field) * W + c;
+  const int col = (tile % tiles_per_field) * WT + c;
   const bool valid = col < nx;
   cpx<T>* base = spec + (size_t)field * N * nx + col;
-  cpx<T>* L = lds + c * lds_line_stride<T>(N);
+  cpx<T>* L = lds + c;
   cpx<T> v[G::R];
 #pragma unroll
   for (int s = 0; s < G::R; ++s) v[s] = valid ? base[(size_t)(t + s * G::TL) * nx] : cpx<T>{0, 0};
-  line_fft<N, false>(v, L, t, tw);
+  line_fft<N, false, WT>(v, L, t, tw);
   const int mx = col < nx / 2 ? col : col - nx;
   const double kx = kx0 * mx;
   double acc = 0.0;
@@ -127,13 +126,17 @@ hipError_t nls_cq_row(Prec p, int nx, int nlines, const void* psi, void* spec, d
 template <typename T>
 static hipError_t cq_col(int ny, int nx, int nfields, void* spec, double* part, const void* tw,
                          double kx0, double ky0, int W, hipStream_t s) {
-  bool ok = dispatch_n(ny, [&](auto nc) {
+  bool ok = false;
+  dispatch_n(ny, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    using G = ColGeom<T, N>;
+    ok = dispatch_w<T, N>(W, [&](auto wc) {
+    constexpr int WT = decltype(wc)::value;
+    using G = ColGeom<T, N, WT>;
     const int tiles = (nx + W - 1) / W;
-    allow_lds((k_nls_cq_col<T, N>), G::lds_bytes(W));
-    hipLaunchKernelGGL((k_nls_cq_col<T, N>), dim3(tiles * nfields), dim3(W * G::TL), G::lds_bytes(W),
+    allow_lds((k_nls_cq_col<T, N, WT>), G::LDS_BYTES);
+    hipLaunchKernelGGL((k_nls_cq_col<T, N, WT>), dim3(tiles * nfields), dim3(G::THREADS), G::LDS_BYTES,
                        s, (cpx<T>*)spec, nx, tiles, part, (const cpx<T>*)tw, kx0, ky0);
+    });
   });
   return ok ? hipGetLastError() : hipErrorInvalidValue;
 }

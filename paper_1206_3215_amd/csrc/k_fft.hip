@@ -29,25 +29,24 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_row_c2c(
 }
 
 // --------------------------------------------------------- C2C columns ---
-template <typename T, int N, bool INV>
-__global__ __launch_bounds__(1024) void k_col_c2c(const cpx<T>* src, cpx<T>* dst, int ncols, int ld,
+template <typename T, int N, bool INV, int WT>
+__global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_col_c2c(const cpx<T>* src, cpx<T>* dst, int ncols, int ld,
                                                   int tiles_per_field, T scale,
                                                   const cpx<T>* __restrict__ tw) {
-  using G = ColGeom<T, N>;
+  using G = ColGeom<T, N, WT>;
   extern __shared__ char smem[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
-  const int W = blockDim.x / G::TL;
-  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  const int c = threadIdx.x % WT, t = threadIdx.x / WT;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int field = tile / tiles_per_field;
-  const int col = (tile % tiles_per_field) * W + c;
+  const int col = (tile % tiles_per_field) * WT + c;
   const bool valid = col < ncols;
   const size_t off = (size_t)field * N * ld + col;
-  cpx<T>* L = lds + c * lds_line_stride<T>(N);
+  cpx<T>* L = lds + c;
   cpx<T> v[G::R];
 #pragma unroll
   for (int s = 0; s < G::R; ++s) v[s] = valid ? src[off + (size_t)(t + s * G::TL) * ld] : cpx<T>{0, 0};
-  line_fft<N, INV>(v, L, t, tw);
+  line_fft<N, INV, WT>(v, L, t, tw);
   if (valid) {
 #pragma unroll
     for (int s = 0; s < G::R; ++s) dst[off + (size_t)(t + s * G::TL) * ld] = v[s] * scale;
@@ -169,23 +168,27 @@ hipError_t fft_row_c2c(Prec p, int n, int nlines, const void* in, void* out, boo
 template <typename T>
 static hipError_t col_c2c(int ny, int ncols, int ld, int nfields, const void* src, void* dst, bool inv,
                           double scale, const void* tw, int W, hipStream_t s) {
-  bool ok = dispatch_n(ny, [&](auto nc) {
+  bool ok = false;
+  dispatch_n(ny, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    using G = ColGeom<T, N>;
+    ok = dispatch_w<T, N>(W, [&](auto wc) {
+    constexpr int WT = decltype(wc)::value;
+    using G = ColGeom<T, N, WT>;
     const int tiles = (ncols + W - 1) / W;
     const int grid = tiles * nfields;
-    const size_t lds = G::lds_bytes(W);
+    const size_t lds = G::LDS_BYTES;
     if (inv) {
-      allow_lds((k_col_c2c<T, N, true>), lds);
-      hipLaunchKernelGGL((k_col_c2c<T, N, true>), dim3(grid), dim3(W * G::TL), lds, s,
+      allow_lds((k_col_c2c<T, N, true, WT>), lds);
+      hipLaunchKernelGGL((k_col_c2c<T, N, true, WT>), dim3(grid), dim3(G::THREADS), lds, s,
                          (const cpx<T>*)src, (cpx<T>*)dst, ncols, ld, tiles, (T)scale,
                          (const cpx<T>*)tw);
     } else {
-      allow_lds((k_col_c2c<T, N, false>), lds);
-      hipLaunchKernelGGL((k_col_c2c<T, N, false>), dim3(grid), dim3(W * G::TL), lds, s,
+      allow_lds((k_col_c2c<T, N, false, WT>), lds);
+      hipLaunchKernelGGL((k_col_c2c<T, N, false, WT>), dim3(grid), dim3(G::THREADS), lds, s,
                          (const cpx<T>*)src, (cpx<T>*)dst, ncols, ld, tiles, (T)scale,
                          (const cpx<T>*)tw);
     }
+    });
   });
   return ok ? hipGetLastError() : hipErrorInvalidValue;
 }
@@ -238,13 +241,21 @@ hipError_t fft_row_c2r(Prec p, int n, int nlines, int ny, const void* in, FieldR
 }
 
 int col_tile_max(Prec p, int n) {
-  const int R = n < 16 ? n : 16;
-  const int TL = n / R;
-  const size_t esz = p == P32 ? 8 : 16;
-  const size_t line = (size_t)(n + n / 16 + 128 / esz) * esz;
-  int W = 1;
-  while (W < 16 && (2 * W) * TL <= 1024 && (size_t)(2 * W) * line <= 150 * 1024) W *= 2;
-  return W;
+  int w = 0;
+  dispatch_n(n, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    w = p == P32 ? ColTiles<float, N>::WMAX : ColTiles<double, N>::WMAX;
+  });
+  return w;
+}
+
+int col_tile_alt(Prec p, int n) {
+  int w = 0;
+  dispatch_n(n, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    w = p == P32 ? ColTiles<float, N>::WALT : ColTiles<double, N>::WALT;
+  });
+  return w;
 }
 
 }  // namespace pst

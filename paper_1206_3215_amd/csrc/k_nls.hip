@@ -29,10 +29,12 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_nls_row(
   const int line = blockIdx.x * G::LPB + lid;
   const bool valid = line < nlines;
   cpx<T>* L = lds + lid * lds_line_stride<T>(N);
-  cpx<T>* g = (cpx<T>*)psi.at(line >> lny) + (size_t)(line & ((1 << lny) - 1)) * N;
+  // lines past the end (a partial last block) recompute the last line and do not store
+  const int lc = valid ? line : nlines - 1;
+  cpx<T>* g = (cpx<T>*)psi.at(lc >> lny) + (size_t)(lc & ((1 << lny) - 1)) * N;
   cpx<T> v[G::R];
 #pragma unroll
-  for (int s = 0; s < G::R; ++s) v[s] = valid ? g[t + s * G::TL] : cpx<T>{0, 0};
+  for (int s = 0; s < G::R; ++s) v[s] = g[t + s * G::TL];
   if constexpr (MODE == 0) {
     line_fft<N, false>(v, L, t, tw);
 #pragma unroll
@@ -53,34 +55,34 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_nls_row(
   }
 }
 
-template <typename T, int N>
-__global__ __launch_bounds__(1024) void k_nls_col(FieldRef psi, int nx, int tiles_per_field,
+template <typename T, int N, int WT>
+__global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_nls_col(FieldRef psi, int nx, int tiles_per_field,
                                                   const cpx<T>* __restrict__ tw,
                                                   const cpx<T>* __restrict__ ex,
                                                   const cpx<T>* __restrict__ ey, T scale) {
-  using G = ColGeom<T, N>;
+  using G = ColGeom<T, N, WT>;
   extern __shared__ char smem[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
-  const int W = blockDim.x / G::TL;
-  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  const int c = threadIdx.x % WT, t = threadIdx.x / WT;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int field = tile / tiles_per_field;
-  const int col = (tile % tiles_per_field) * W + c;
+  const int col = (tile % tiles_per_field) * WT + c;
   const bool valid = col < nx;
-  cpx<T>* base = (cpx<T>*)psi.at(field) + col;
-  cpx<T>* L = lds + c * lds_line_stride<T>(N);
+  const int cc = valid ? col : nx - 1;  // columns past the end recompute the last one, unstored
+  cpx<T>* base = (cpx<T>*)psi.at(field) + cc;
+  cpx<T>* L = lds + c;
   cpx<T> v[G::R];
 #pragma unroll
-  for (int s = 0; s < G::R; ++s) v[s] = valid ? base[(size_t)(t + s * G::TL) * nx] : cpx<T>{0, 0};
-  line_fft<N, false>(v, L, t, tw);
-  const cpx<T> exm = valid ? ex[col] : cpx<T>{0, 0};
+  for (int s = 0; s < G::R; ++s) v[s] = base[(size_t)(t + s * G::TL) * nx];
+  line_fft<N, false, WT>(v, L, t, tw);
+  const cpx<T> exm = ex[cc];
 #pragma unroll
   for (int s = 0; s < G::R; ++s) {
     const cpx<T> w = v[s] * scale;
     const cpx<T> wx = w + cmul(w, exm);
     v[s] = wx + cmul(wx, ey[t + s * G::TL]);
   }
-  line_fft<N, true>(v, L, t, tw);
+  line_fft<N, true, WT>(v, L, t, tw);
   if (valid) {
 #pragma unroll
     for (int s = 0; s < G::R; ++s) base[(size_t)(t + s * G::TL) * nx] = v[s];
@@ -120,14 +122,18 @@ hipError_t nls_row(Prec p, int nx, int nlines, int ny, FieldRef psi, int mode, d
 template <typename T>
 static hipError_t col(int ny, int nx, int nfields, FieldRef psi, const void* tw, const void* ex,
                       const void* ey, int W, hipStream_t s) {
-  bool ok = dispatch_n(ny, [&](auto nc) {
+  bool ok = false;
+  dispatch_n(ny, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    using G = ColGeom<T, N>;
+    ok = dispatch_w<T, N>(W, [&](auto wc) {
+    constexpr int WT = decltype(wc)::value;
+    using G = ColGeom<T, N, WT>;
     const int tiles = (nx + W - 1) / W;
-    allow_lds((k_nls_col<T, N>), G::lds_bytes(W));
-    hipLaunchKernelGGL((k_nls_col<T, N>), dim3(tiles * nfields), dim3(W * G::TL), G::lds_bytes(W), s,
+    allow_lds((k_nls_col<T, N, WT>), G::LDS_BYTES);
+    hipLaunchKernelGGL((k_nls_col<T, N, WT>), dim3(tiles * nfields), dim3(G::THREADS), G::LDS_BYTES, s,
                        psi, nx, tiles, (const cpx<T>*)tw, (const cpx<T>*)ex,
                        (const cpx<T>*)ey, (T)(1.0 / ((double)nx * N)));
+    });
   });
   return ok ? hipGetLastError() : hipErrorInvalidValue;
 }

@@ -84,33 +84,32 @@ struct NsColArgs {
   int nx, kx_cut, ky_cut;
 };
 
-template <typename T, int N, int MODE>
-__global__ __launch_bounds__(1024) void k_ns_col(const cpx<T>* NH, cpx<T>* WN, cpx<T>* Q, cpx<T>* DK,
+template <typename T, int N, int MODE, int WT>
+__global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_ns_col(const cpx<T>* NH, cpx<T>* WN, cpx<T>* Q, cpx<T>* DK,
                                                  cpx<T>* D, size_t dstride, cpx<T>* OUT, double* part,
                                                  int tiles_per_field, const int* done, NsColArgs a,
                                                  const cpx<T>* __restrict__ tw) {
-  using G = ColGeom<T, N>;
+  using G = ColGeom<T, N, WT>;
   constexpr int MY = N;  // column length (ny)
   extern __shared__ char smem[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
   __shared__ double red[1024];
   const int ncols = a.nx / 2 + 1;
-  const int Wt = blockDim.x / G::TL;
-  const int c = threadIdx.x % Wt, t = threadIdx.x / Wt;
+  const int c = threadIdx.x % WT, t = threadIdx.x / WT;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int field = tile / tiles_per_field;
   if (MODE == NS_ITER && done[field]) return;  // uniform: a block is one field
-  const int col = (tile % tiles_per_field) * Wt + c;
+  const int col = (tile % tiles_per_field) * WT + c;
   const bool valid = col < ncols;
   const size_t off = (size_t)field * MY * ncols + col;
-  cpx<T>* L = lds + c * lds_line_stride<T>(MY);
+  cpx<T>* L = lds + c;
   auto at = [&](int s) { return off + (size_t)(t + s * G::TL) * ncols; };
   cpx<T> w[G::R], v[G::R];
 
   if constexpr (MODE == NS_EXIT) {
 #pragma unroll
     for (int s = 0; s < G::R; ++s) v[s] = valid ? WN[at(s)] + DK[at(s)] : cpx<T>{0, 0};
-    line_fft<MY, true>(v, L, t, tw);
+    line_fft<MY, true, WT>(v, L, t, tw);
     if (valid) {
 #pragma unroll
       for (int s = 0; s < G::R; ++s) OUT[at(s)] = v[s];
@@ -124,7 +123,7 @@ __global__ __launch_bounds__(1024) void k_ns_col(const cpx<T>* NH, cpx<T>* WN, c
     // N hybrid -> spectrum (entry: omega's x-transform -> w^n)
 #pragma unroll
     for (int s = 0; s < G::R; ++s) v[s] = valid ? NH[at(s)] : cpx<T>{0, 0};
-    line_fft<MY, false>(v, L, t, tw);
+    line_fft<MY, false, WT>(v, L, t, tw);
     if constexpr (MODE == NS_ENTRY) {
 #pragma unroll
       for (int s = 0; s < G::R; ++s) {
@@ -193,7 +192,7 @@ __global__ __launch_bounds__(1024) void k_ns_col(const cpx<T>* NH, cpx<T>* WN, c
         const T f = q == 0 ? kyd * ik2 : q == 1 ? kxd * dsc : q == 2 ? kxd * ik2 : kyd * dsc;
         v[s] = mul_i(w[s]) * f;
       }
-      line_fft<MY, true>(v, L, t, tw);
+      line_fft<MY, true, WT>(v, L, t, tw);
       if (valid) {
 #pragma unroll
         for (int s = 0; s < G::R; ++s) D[q * dstride + at(s)] = v[s];
@@ -247,26 +246,25 @@ __global__ __launch_bounds__(256) void k_ns_finish(int ncols, const double* part
 
 // Diagnostics: energy (1/2) sum_{k != 0} |w|^2/|k|^2 and enstrophy
 // (1/2) sum |w|^2 over the full spectrum (half-spectrum weights).
-template <typename T, int N>
-__global__ __launch_bounds__(1024) void k_ns_cq_col(const cpx<T>* XH, double* part, int nx, int tiles_per_field,
+template <typename T, int N, int WT>
+__global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_ns_cq_col(const cpx<T>* XH, double* part, int nx, int tiles_per_field,
                                                     double kx0, double ky0, const cpx<T>* __restrict__ tw) {
-  using G = ColGeom<T, N>;
+  using G = ColGeom<T, N, WT>;
   extern __shared__ char smem[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
   __shared__ double red[1024];
   const int ncols = nx / 2 + 1;
-  const int Wt = blockDim.x / G::TL;
-  const int c = threadIdx.x % Wt, t = threadIdx.x / Wt;
+  const int c = threadIdx.x % WT, t = threadIdx.x / WT;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int field = tile / tiles_per_field;
-  const int col = (tile % tiles_per_field) * Wt + c;
+  const int col = (tile % tiles_per_field) * WT + c;
   const bool valid = col < ncols;
   const size_t off = (size_t)field * N * ncols + col;
-  cpx<T>* L = lds + c * lds_line_stride<T>(N);
+  cpx<T>* L = lds + c;
   cpx<T> v[G::R];
 #pragma unroll
   for (int s = 0; s < G::R; ++s) v[s] = valid ? XH[off + (size_t)(t + s * G::TL) * ncols] : cpx<T>{0, 0};
-  line_fft<N, false>(v, L, t, tw);
+  line_fft<N, false, WT>(v, L, t, tw);
   const double kx = kx0 * col;
   double en = 0.0, zz = 0.0;
 #pragma unroll
@@ -331,22 +329,26 @@ hipError_t ns_row(Prec p, int nx, int nlines, int ny, const void* D, size_t dstr
 template <typename T>
 static hipError_t col(int mode, int ny, int nfields, const NsPtrs& P, const NsScalars& S, const int* done,
                       const void* tw, int Wt, hipStream_t s) {
-  bool ok = dispatch_n(ny, [&](auto nc) {
+  bool ok = false;
+  dispatch_n(ny, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    using G = ColGeom<T, N>;
+    ok = dispatch_w<T, N>(Wt, [&](auto wc) {
+    constexpr int WT = decltype(wc)::value;
+    using G = ColGeom<T, N, WT>;
     const int ncols = S.nx / 2 + 1;
     const int tiles = (ncols + Wt - 1) / Wt;
     NsColArgs a{S.kx0, S.ky0, S.hnu, S.qdt, S.nscale, S.dscale, S.nx, S.kx_cut, S.ky_cut};
     auto go = [&](auto kern) {
-      allow_lds(kern, G::lds_bytes(Wt));
-      hipLaunchKernelGGL(kern, dim3(tiles * nfields), dim3(Wt * G::TL), G::lds_bytes(Wt), s, (const cpx<T>*)P.NH,
+      allow_lds(kern, G::LDS_BYTES);
+      hipLaunchKernelGGL(kern, dim3(tiles * nfields), dim3(G::THREADS), G::LDS_BYTES, s, (const cpx<T>*)P.NH,
                          (cpx<T>*)P.WN, (cpx<T>*)P.Q, (cpx<T>*)P.DK, (cpx<T>*)P.D, P.dstride, (cpx<T>*)P.OUT,
                          P.part, tiles, done, a, (const cpx<T>*)tw);
     };
-    if (mode == NS_ENTRY) go(k_ns_col<T, N, NS_ENTRY>);
-    else if (mode == NS_FIRST) go(k_ns_col<T, N, NS_FIRST>);
-    else if (mode == NS_ITER) go(k_ns_col<T, N, NS_ITER>);
-    else go(k_ns_col<T, N, NS_EXIT>);
+    if (mode == NS_ENTRY) go(k_ns_col<T, N, NS_ENTRY, WT>);
+    else if (mode == NS_FIRST) go(k_ns_col<T, N, NS_FIRST, WT>);
+    else if (mode == NS_ITER) go(k_ns_col<T, N, NS_ITER, WT>);
+    else go(k_ns_col<T, N, NS_EXIT, WT>);
+    });
   });
   return ok ? hipGetLastError() : hipErrorInvalidValue;
 }
@@ -368,13 +370,17 @@ hipError_t ns_finish(int nfields, int ncols, const double* part, double vol, dou
 template <typename T>
 static hipError_t cqcol(int ny, int nx, int nfields, const void* XH, double* part, double kx0, double ky0,
                         const void* tw, int Wt, hipStream_t s) {
-  bool ok = dispatch_n(ny, [&](auto nc) {
+  bool ok = false;
+  dispatch_n(ny, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    using G = ColGeom<T, N>;
+    ok = dispatch_w<T, N>(Wt, [&](auto wc) {
+    constexpr int WT = decltype(wc)::value;
+    using G = ColGeom<T, N, WT>;
     const int tiles = (nx / 2 + 1 + Wt - 1) / Wt;
-    allow_lds(k_ns_cq_col<T, N>, G::lds_bytes(Wt));
-    hipLaunchKernelGGL((k_ns_cq_col<T, N>), dim3(tiles * nfields), dim3(Wt * G::TL), G::lds_bytes(Wt), s,
+    allow_lds(k_ns_cq_col<T, N, WT>, G::LDS_BYTES);
+    hipLaunchKernelGGL((k_ns_cq_col<T, N, WT>), dim3(tiles * nfields), dim3(G::THREADS), G::LDS_BYTES, s,
                        (const cpx<T>*)XH, part, nx, tiles, kx0, ky0, (const cpx<T>*)tw);
+    });
   });
   return ok ? hipGetLastError() : hipErrorInvalidValue;
 }

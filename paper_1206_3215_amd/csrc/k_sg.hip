@@ -92,21 +92,20 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_row(
 }
 
 // Column pass over the nx/2+1 half-spectrum columns.
-template <typename T, int N>
-__global__ __launch_bounds__(1024) void k_sg_col(const cpx<T>* U, const cpx<T>* S, cpx<T>* W, int ncols,
+template <typename T, int N, int WT>
+__global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_sg_col(const cpx<T>* U, const cpx<T>* S, cpx<T>* W, int ncols,
                                                  int tiles_per_field, const cpx<T>* __restrict__ tw,
                                                  T kx0, T ky0, T dt2q, T cnum, T c2num, T sc) {
-  using G = ColGeom<T, N>;
+  using G = ColGeom<T, N, WT>;
   extern __shared__ char smem[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
-  const int Wt = blockDim.x / G::TL;
-  const int c = threadIdx.x % Wt, t = threadIdx.x / Wt;
+  const int c = threadIdx.x % WT, t = threadIdx.x / WT;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int field = tile / tiles_per_field;
-  const int col = (tile % tiles_per_field) * Wt + c;
+  const int col = (tile % tiles_per_field) * WT + c;
   const bool valid = col < ncols;
   const size_t off = (size_t)field * N * ncols + col;
-  cpx<T>* L = lds + c * lds_line_stride<T>(N);
+  cpx<T>* L = lds + c;
   cpx<T> u[G::R], s_[G::R];
 #pragma unroll
   for (int s = 0; s < G::R; ++s) {
@@ -114,8 +113,8 @@ __global__ __launch_bounds__(1024) void k_sg_col(const cpx<T>* U, const cpx<T>* 
     u[s] = valid ? U[i] : cpx<T>{0, 0};
     s_[s] = valid ? S[i] : cpx<T>{0, 0};
   }
-  line_fft<N, false>(u, L, t, tw);
-  line_fft<N, false>(s_, L, t, tw);
+  line_fft<N, false, WT>(u, L, t, tw);
+  line_fft<N, false, WT>(s_, L, t, tw);
   const T kx = kx0 * (T)col;
   const T kx2 = kx * kx;
 #pragma unroll
@@ -128,7 +127,7 @@ __global__ __launch_bounds__(1024) void k_sg_col(const cpx<T>* U, const cpx<T>* 
     const T c1m = T(-2) * cnum * a * inv * sc, c2 = c2num * inv * sc;
     u[s] = cpx<T>{c1m * u[s].re - c2 * s_[s].re, c1m * u[s].im - c2 * s_[s].im};
   }
-  line_fft<N, true>(u, L, t, tw);
+  line_fft<N, true, WT>(u, L, t, tw);
   if (valid) {
 #pragma unroll
     for (int s = 0; s < G::R; ++s) W[off + (size_t)(t + s * G::TL) * ncols] = u[s];
@@ -178,26 +177,25 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_h_row(
 
 // Column pass: sum over the half spectrum of w(mx) |k|^2 |2 ubar_hat|^2 with
 // w = 1 on the self-conjugate columns mx = 0, nx/2 and 2 elsewhere.
-template <typename T, int N>
-__global__ __launch_bounds__(1024) void k_sg_h_col(cpx<T>* UB, double* part, int ncols, int nx,
+template <typename T, int N, int WT>
+__global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_sg_h_col(cpx<T>* UB, double* part, int ncols, int nx,
                                                    int tiles_per_field, const cpx<T>* __restrict__ tw,
                                                    double kx0, double ky0) {
-  using G = ColGeom<T, N>;
+  using G = ColGeom<T, N, WT>;
   extern __shared__ char smem[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
   __shared__ double red[1024];
-  const int Wt = blockDim.x / G::TL;
-  const int c = threadIdx.x % Wt, t = threadIdx.x / Wt;
+  const int c = threadIdx.x % WT, t = threadIdx.x / WT;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int field = tile / tiles_per_field;
-  const int col = (tile % tiles_per_field) * Wt + c;
+  const int col = (tile % tiles_per_field) * WT + c;
   const bool valid = col < ncols;
   const size_t off = (size_t)field * N * ncols + col;
-  cpx<T>* L = lds + c * lds_line_stride<T>(N);
+  cpx<T>* L = lds + c;
   cpx<T> v[G::R];
 #pragma unroll
   for (int s = 0; s < G::R; ++s) v[s] = valid ? UB[off + (size_t)(t + s * G::TL) * ncols] : cpx<T>{0, 0};
-  line_fft<N, false>(v, L, t, tw);
+  line_fft<N, false, WT>(v, L, t, tw);
   const double kx = kx0 * col;
   const double w = (col == 0 || col == nx / 2) ? 1.0 : 2.0;
   double acc = 0.0;
@@ -268,15 +266,19 @@ template <typename T>
 static hipError_t col(int ny, int nx, int nfields, const void* U, const void* S, void* W, const void* tw,
                       double kx0, double ky0, double dt2q, double cnum, double c2num, double sc, int Wt,
                       hipStream_t s) {
-  bool ok = dispatch_n(ny, [&](auto nc) {
+  bool ok = false;
+  dispatch_n(ny, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    using G = ColGeom<T, N>;
+    ok = dispatch_w<T, N>(Wt, [&](auto wc) {
+    constexpr int WT = decltype(wc)::value;
+    using G = ColGeom<T, N, WT>;
     const int ncols = nx / 2 + 1;
     const int tiles = (ncols + Wt - 1) / Wt;
-    allow_lds(k_sg_col<T, N>, G::lds_bytes(Wt));
-    hipLaunchKernelGGL((k_sg_col<T, N>), dim3(tiles * nfields), dim3(Wt * G::TL), G::lds_bytes(Wt), s,
+    allow_lds(k_sg_col<T, N, WT>, G::LDS_BYTES);
+    hipLaunchKernelGGL((k_sg_col<T, N, WT>), dim3(tiles * nfields), dim3(G::THREADS), G::LDS_BYTES, s,
                        (const cpx<T>*)U, (const cpx<T>*)S, (cpx<T>*)W, ncols, tiles, (const cpx<T>*)tw,
                        (T)kx0, (T)ky0, (T)dt2q, (T)cnum, (T)c2num, (T)sc);
+    });
   });
   return ok ? hipGetLastError() : hipErrorInvalidValue;
 }
@@ -311,14 +313,18 @@ hipError_t sg_h_row(Prec p, int nx, int nlines, const void* f0, const void* f1, 
 template <typename T>
 static hipError_t hcol(int ny, int nx, int nfields, void* UB, double* part, const void* tw, double kx0,
                        double ky0, int Wt, hipStream_t s) {
-  bool ok = dispatch_n(ny, [&](auto nc) {
+  bool ok = false;
+  dispatch_n(ny, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    using G = ColGeom<T, N>;
+    ok = dispatch_w<T, N>(Wt, [&](auto wc) {
+    constexpr int WT = decltype(wc)::value;
+    using G = ColGeom<T, N, WT>;
     const int ncols = nx / 2 + 1;
     const int tiles = (ncols + Wt - 1) / Wt;
-    allow_lds(k_sg_h_col<T, N>, G::lds_bytes(Wt));
-    hipLaunchKernelGGL((k_sg_h_col<T, N>), dim3(tiles * nfields), dim3(Wt * G::TL), G::lds_bytes(Wt), s,
+    allow_lds(k_sg_h_col<T, N, WT>, G::LDS_BYTES);
+    hipLaunchKernelGGL((k_sg_h_col<T, N, WT>), dim3(tiles * nfields), dim3(G::THREADS), G::LDS_BYTES, s,
                        (cpx<T>*)UB, part, ncols, nx, tiles, (const cpx<T>*)tw, kx0, ky0);
+    });
   });
   return ok ? hipGetLastError() : hipErrorInvalidValue;
 }

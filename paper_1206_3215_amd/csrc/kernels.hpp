@@ -33,16 +33,44 @@ struct RowGeom {
   static constexpr size_t LDS_BYTES = (size_t)LPB * lds_line_stride<T>(N) * sizeof(cpx<T>);
 };
 
-// Column pass: W adjacent columns per block (W chosen at run time), thread
-// (c, t) with c fastest so that a wave reads W consecutive elements of a
-// row per instruction.
-template <typename T, int N>
+// Column pass: W adjacent columns per block, thread (c, t) with c fastest so
+// that a wave reads W consecutive elements of a row per instruction; the W
+// lines are interleaved in LDS (slot * W + c).
+template <typename T, int N, int W>
 struct ColGeom {
   static constexpr int R = line_radix(N);
   static constexpr int TL = N / R;
-  static constexpr int MAX_THREADS = 1024;
-  static size_t lds_bytes(int W) { return (size_t)W * lds_line_stride<T>(N) * sizeof(cpx<T>); }
+  static constexpr int THREADS = W * TL;
+  static constexpr size_t LDS_BYTES = (size_t)W * lds_line_len(N) * sizeof(cpx<T>);
 };
+
+// Column tiles compiled for a column length: the largest W with W*N/16 <=
+// 1024 threads, W <= 16 and <= 150 KB of LDS, and half of it.  The
+// autotuner chooses between the two.
+template <typename T, int N>
+struct ColTiles {
+  static constexpr int TL = N / line_radix(N);
+  static constexpr int fit(int w) {
+    return (w * TL <= 1024 && (size_t)w * lds_line_len(N) * sizeof(cpx<T>) <= 150 * 1024) ? w : 0;
+  }
+  static constexpr int WMAX = fit(16) ? 16 : fit(8) ? 8 : fit(4) ? 4 : fit(2) ? 2 : 1;
+  static constexpr int WALT = WMAX > 1 ? WMAX / 2 : 1;
+};
+
+// Calls f(IntC<W>) for the compiled tile equal to w (false if none).
+template <typename T, int N, class F>
+bool dispatch_w(int w, F&& f) {
+  using CT = ColTiles<T, N>;
+  if (w == CT::WMAX) {
+    f(std::integral_constant<int, CT::WMAX>{});
+    return true;
+  }
+  if (w == CT::WALT) {
+    f(std::integral_constant<int, CT::WALT>{});
+    return true;
+  }
+  return false;
+}
 
 // Blocks are handed to the 8 XCDs of the chip round robin (block b runs on
 // XCD b mod 8).  Give each XCD a contiguous range of tiles, so that the
@@ -56,14 +84,15 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
 // v * exp(-i theta), written as v + v*(cos(theta) - 1 - i sin(theta)) with
 // cos(theta) - 1 = -2 sin^2(theta/2): for the small angles of a time step
 // the correction is tiny, so rounding does not bias |v| (a rounded
-// cos(theta) near 1 would).  Short Taylor series for |theta| <= 1/8, library
+// cos(theta) near 1 would).  Short Taylor series for small angles, library
 // sincos otherwise.
 __device__ __forceinline__ cpx<float> rotate_neg(cpx<float> v, float th) {
   float cm1, s;
-  if (fabsf(th) <= 0.125f) {
+  if (fabsf(th) <= 0.03125f) {
+    // |theta| <= 2^-5: truncation below 2e-12 (cos - 1) and 3e-10 (sin)
     const float t2 = th * th;
-    cm1 = t2 * (-0.5f + t2 * (1.0f / 24 + t2 * (-1.0f / 720 + t2 * (1.0f / 40320))));
-    s = th * (1.0f + t2 * (-1.0f / 6 + t2 * (1.0f / 120 + t2 * (-1.0f / 5040))));
+    cm1 = t2 * (-0.5f + t2 * (1.0f / 24));
+    s = th * (1.0f - t2 * (1.0f / 6));
   } else {
     float sh, ch;
     sincosf(0.5f * th, &sh, &ch);

@@ -30,9 +30,10 @@ inline FieldRef contiguous(const void* p, size_t field_bytes) {
 // Status bits latched by kernels into a plan's device status word.
 enum : int { ST_NONFINITE = 1, ST_NOT_CONVERGED = 2 };
 
-// Column-pass tile: W adjacent columns per block, bounded by the block size
-// and by the LDS footprint.
+// Column-pass tiles compiled for length n: the widest (W columns per block,
+// bounded by the block size and the LDS footprint) and its half.
 int col_tile_max(Prec p, int n);
+int col_tile_alt(Prec p, int n);
 
 // ----------------------------------------------------------------- FFT ---
 // Row pass over nlines contiguous complex lines of length n: out = FFT(in)

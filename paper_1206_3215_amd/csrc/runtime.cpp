@@ -319,6 +319,15 @@ pst_status fft2d_exec(pst_plan pl, const void* in, void* out, int sign) {
                    "c2r row pass");
 }
 
+pst_status pst_set_column_tile(pst_plan pl, int w) {
+  if (pl == nullptr) return fail(PST_ERR_INVALID, "plan is NULL");
+  if (w != col_tile_max(pl->P, pl->ny) && w != col_tile_alt(pl->P, pl->ny))
+    return fail(PST_ERR_INVALID, "column tile %d is not compiled for ny=%d (use %d or %d)", w, pl->ny,
+                col_tile_max(pl->P, pl->ny), col_tile_alt(pl->P, pl->ny));
+  pl->Wcol = w;
+  return PST_OK;
+}
+
 pst_status pst_profile_enable(pst_plan pl, int enable) {
   if (pl == nullptr) return fail(PST_ERR_INVALID, "plan is NULL");
   pl->prof = enable != 0;

@@ -372,6 +372,95 @@ pst_status ns_step(pst_plan pl, void* omega, const pst_ns_params* p, int nsteps,
 
 }  // extern "C"
 
+// ------------------------------------------------------------ autotune ---
+extern "C" pst_status pst_autotune(pst_plan pl, pst_eq eq, int* chosen);
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, int> g_tuned;  // (eq, prec, nx, ny) -> tile
+}  // namespace
+
+// ptab: zeroed propagator stand-in of max(nx, ny) complex entries.
+static pst_status time_col(Plan* pl, pst_eq eq, int w, const void* ptab, float* ms) {
+  const int nx = pl->nx, ny = pl->ny, B = pl->batch;
+  hipStream_t s = pl->stream;
+  auto launch = [&]() -> hipError_t {
+    if (eq == PST_NLS)
+      return nls_col(pl->P, ny, nx, B, contiguous(ws_at(pl, pl->off_spec), (size_t)nx * ny * pl->csize), pl->tw_y,
+                     ptab, ptab, w, s);
+    if (eq == PST_SG)
+      return sg_col(pl->P, ny, nx, B, ws_at(pl, pl->off_spec), ws_at(pl, pl->off_spec2), ws_at(pl, pl->off_spec3),
+                    pl->tw_y, 1.0, 1.0, 1e-4, 2.0, 1e-4, 1e-6, w, s);
+    NsPtrs P;
+    const int h = nx / 2 + 1;
+    P.Q = ws_at(pl, pl->off_spec);
+    P.WN = ws_at(pl, pl->off_spec2);
+    P.DK = ws_at(pl, pl->off_spec3);
+    P.NH = ws_at(pl, pl->off_spec4);
+    P.OUT = ws_at(pl, pl->off_spec4);
+    P.D = ws_at(pl, pl->off_hyb);
+    P.dstride = (size_t)B * ny * h;
+    P.part = static_cast<double*>(ws_at(pl, pl->off_colpart));
+    NsScalars S{2 * M_PI, 2 * M_PI, 5e-7, 5e-4, 0.5, 1.0 / ((double)nx * ny), nx, (nx - 1) / 3, (ny - 1) / 3};
+    return ns_col(pl->P, 1, ny, B, P, S, static_cast<int*>(ws_at(pl, pl->off_nsstate)), pl->tw_y, w, s);
+  };
+  TRY(hip_check(launch(), "autotune warm-up"));
+  hipEvent_t a, b;
+  TRY(hip_check(hipEventCreate(&a), "hipEventCreate"));
+  TRY(hip_check(hipEventCreate(&b), "hipEventCreate"));
+  hipEventRecord(a, s);
+  pst_status st = PST_OK;
+  for (int i = 0; i < 5 && st == PST_OK; ++i) st = hip_check(launch(), "autotune launch");
+  hipEventRecord(b, s);
+  if (st == PST_OK) st = hip_check(hipEventSynchronize(b), "hipEventSynchronize");
+  if (st == PST_OK) st = hip_check(hipEventElapsedTime(ms, a, b), "hipEventElapsedTime");
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return st;
+}
+
+extern "C" pst_status pst_autotune(pst_plan pl, pst_eq eq, int* chosen) {
+  if (pl == nullptr) return fail(PST_ERR_INVALID, "plan is NULL");
+  if (eq != PST_NLS && eq != PST_SG && eq != PST_NS) return fail(PST_ERR_INVALID, "unknown equation %d", (int)eq);
+  TRY(need_kind(pl, eq == PST_NLS ? PST_C2C : PST_R2C, "pst_autotune"));
+  TRY(ensure_workspace(pl));
+  const auto key = std::make_tuple((int)eq, (int)pl->prec, pl->nx, pl->ny);
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+      pl->Wcol = it->second;
+      if (chosen) *chosen = pl->Wcol;
+      return PST_OK;
+    }
+  }
+  // workspace contents are irrelevant to the timing; start from zeros
+  TRY(hip_check(hipMemsetAsync(pl->ws, 0, pl->ws_need, pl->stream), "clear workspace"));
+  void* ptab = nullptr;
+  const size_t pbytes = (size_t)std::max(pl->nx, pl->ny) * pl->csize;
+  TRY(hip_check(hipMalloc(&ptab, pbytes), "hipMalloc(autotune table)"));
+  pl->owned.push_back(ptab);
+  TRY(hip_check(hipMemsetAsync(ptab, 0, pbytes, pl->stream), "clear autotune table"));
+  const int cand[2] = {col_tile_max(pl->P, pl->ny), col_tile_alt(pl->P, pl->ny)};
+  int best = cand[0];
+  float best_ms = 1e30f;
+  for (int i = 0; i < 2; ++i) {
+    if (i == 1 && cand[1] == cand[0]) break;
+    float ms = 0.f;
+    TRY(time_col(pl, eq, cand[i], ptab, &ms));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = cand[i];
+    }
+  }
+  pl->Wcol = best;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tuned[key] = best;
+  }
+  if (chosen) *chosen = best;
+  return PST_OK;
+}
+
 // ------------------------------------------------------------ batching ---
 // solve_batch groups requests that share (equation, nx, ny, precision,
 // parameters).  Each group runs on an internal plan whose capacity is the
@@ -425,6 +514,7 @@ pst_status batch_plan(const pst_request& r, int cap, hipStream_t s, BatchPlan** 
   BatchPlan bp;
   TRY(fft2d_plan(r.nx, r.ny, r.eq == PST_NLS ? PST_C2C : PST_R2C, r.prec, cap, s, &bp.pl));
   TRY(ensure_workspace(bp.pl));
+  TRY(pst_autotune(bp.pl, r.eq, nullptr));
   void* p = nullptr;
   TRY(hip_check(hipMalloc(&p, (size_t)cap * (4 * sizeof(void*) + sizeof(int)) + 256), "hipMalloc(tables)"));
   bp.pl->owned.push_back(p);

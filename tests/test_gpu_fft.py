@@ -62,3 +62,22 @@ def test_c2r_ignores_imaginary_dc_and_nyquist():
     out = torch.empty((1, ny, nx), dtype=torch.float64, device="cuda")
     plan.fft2d_exec(to_dev(X, torch, torch.complex128), out, +1)
     assert rel_err(to_host(out)[0], sp.irfft2(X[0], (ny, nx))) < 1e-13
+
+
+@pytest.mark.parametrize("eq,kind,n", [("nls", 0, 4096), ("nls", 0, 256), ("sg", 1, 2048), ("ns", 1, 1024)])
+def test_autotune_picks_a_compiled_tile_and_keeps_results(eq, kind, n):
+    torch = need_gpu()
+    from paper_1206_3215_amd import binding as b
+    from paper_1206_3215_amd import inputs
+    plan = b.Plan(n, n, kind, b.PST_FP32, 1)
+    w = plan.autotune(eq)
+    assert w in (1, 2, 4, 8, 16)
+    if eq == "nls":
+        d = inputs.PAPER_DOMAIN
+        psi0 = inputs.nls_gaussian(n, n, d, seed=0)[None]
+        p1 = b.Plan(n, n, kind, b.PST_FP32, 1)            # default tile
+        a = to_dev(psi0, torch, torch.complex64)
+        c = a.clone()
+        p1.nls_step(a, d, 1e-3, 1.0, 3)
+        plan.nls_step(c, d, 1e-3, 1.0, 3)
+        assert np.array_equal(to_host(a), to_host(c))     # tiling never changes the arithmetic
