@@ -185,7 +185,7 @@ def main():
     d = inputs.PAPER_DOMAIN
     dt, g = 1e-3, 1.0
     plan = b.Plan(n, n, b.PST_C2C, prec, 1)
-    col_tile = plan.autotune("nls")
+    col_variant = plan.autotune("nls")
     psi = torch.from_numpy(inputs.nls_gaussian(n, n, d, seed=0)).to("cuda", plan.complex_dtype)
     psi = psi.reshape(1, n, n).contiguous()
     q0 = plan.conserved_quantities("nls", psi, d=d, dt=dt, g=g)
@@ -249,7 +249,7 @@ def main():
                      "avg_launch_us": avg_s * 1e6, "bytes_per_launch_alg": alg_bytes},
         "pct_hbm_roofline_step": value * 2 * BYTES_PER_PT_PASS[prec] / (HBM_PEAK_GBS * 1e9),
         "passes_avg_us": {k: (v[0] / max(v[1], 1)) * 1e3 for k, v in passes.items()},
-        "column_tile": col_tile,
+        "column_variant": col_variant,
         "copy_GBps": copy_gbs,
         "mass_rel_drift": float(q1[0, 0] / q0[0, 0] - 1),
         "energy_rel_drift": float(q1[0, 1] / q0[0, 1] - 1),

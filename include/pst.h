@@ -203,18 +203,36 @@ const char* pst_last_error(void);
 /* Library version string. */
 const char* pst_version(void);
 
+/* Column tile variants.  Column passes (lines along y) run W adjacent
+ * columns per block.  Variant 0, the default, exists for every length n:
+ * the widest W that fits 1024 threads and 150 KB of LDS, 16 values of a line
+ * per thread, complex values exchanged through LDS between stages.
+ * Single-field column passes (NLS steps and C2C transforms) of FP32 lines of
+ * 4096 and more have two more variants that let two blocks share a CU:
+ *   1: the same W, 32 values per thread, real and imaginary parts exchanged
+ *      one after the other (half the threads and half the LDS per block);
+ *   2: the same W, 16 values per thread, the split exchange, registers
+ *      capped so that two 1024-thread blocks fit a CU.
+ * For every other pass and length, variant 1 is half of variant 0's W.
+ * pst_column_variant_info reports (columns per block, values per thread,
+ * split exchange 0/1) of variant for length n; single_field != 0 asks about
+ * the single-field passes.  PST_ERR_INVALID if n is not a supported length
+ * or the variant does not exist. */
+pst_status pst_column_variant_info(pst_prec prec, int n, int variant, int single_field, int* columns,
+                                   int* values_per_thread, int* split);
+
 /* Autotuning (not in the paper, which notes that launch parameters chosen
  * by the compiler ran 2x slower and that autotuning would help): times the
- * column pass of equation eq on this plan with each compiled column tile
- * width (columns per block) on workspace data, keeps the fastest in the plan
- * and remembers it for later plans of the same (eq, precision, nx, ny) in
- * this process.  Synchronises.  *chosen (may be NULL) receives the width. */
+ * column pass of equation eq on this plan with each column variant on
+ * workspace data, keeps the fastest in the plan and remembers it for later
+ * plans of the same (eq, precision, nx, ny) in this process.  Synchronises.
+ * *chosen (may be NULL) receives the variant. */
 pst_status pst_autotune(pst_plan plan, pst_eq eq, int* chosen);
 
-/* Column tile (columns per block) used by this plan's column passes.  w must
- * be one of the widths compiled for length ny (the widest that fits the
- * block and LDS limits, or half of it); otherwise PST_ERR_INVALID. */
-pst_status pst_set_column_tile(pst_plan plan, int w);
+/* Column variant used by this plan's column passes of length ny (0 by
+ * default).  PST_ERR_INVALID if the variant does not exist for ny and the
+ * plan's kind (C2C plans: single-field variants; R2C plans: two-line). */
+pst_status pst_set_column_variant(pst_plan plan, int variant);
 
 /* Per-pass timing.  While enabled, every pass kernel that plan launches is
  * bracketed by a pair of HIP events recorded on the plan's stream.

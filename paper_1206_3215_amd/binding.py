@@ -69,7 +69,9 @@ _SIGS = {
     "pst_sync_status": [_vp, C.POINTER(C.c_int)],
     "solve_batch": [C.POINTER(Request), C.c_int, _vp],
     "pst_autotune": [_vp, C.c_int, C.POINTER(C.c_int)],
-    "pst_set_column_tile": [_vp, C.c_int],
+    "pst_set_column_variant": [_vp, C.c_int],
+    "pst_column_variant_info": [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                C.POINTER(C.c_int)],
     "pst_profile_enable": [_vp, C.c_int],
     "pst_profile_read": [_vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)],
     "pst_last_error": [],
@@ -182,13 +184,18 @@ class Plan:
         return out.reshape(self.batch, 4)
 
     def autotune(self, eq: str) -> int:
-        """Pick the fastest compiled column tile for this plan; returns it."""
+        """Pick the fastest column variant for this plan; returns it."""
         w = C.c_int()
         check(lib.pst_autotune(self.handle, EQ[eq], C.byref(w)), "pst_autotune")
         return w.value
 
-    def set_column_tile(self, w: int) -> None:
-        check(lib.pst_set_column_tile(self.handle, int(w)), "pst_set_column_tile")
+    def set_column_variant(self, variant: int) -> None:
+        check(lib.pst_set_column_variant(self.handle, int(variant)), "pst_set_column_variant")
+
+    def column_variants(self) -> list:
+        """[(columns per block, values per thread, split)] of every column
+        variant compiled for this plan's ny and kind, by variant number."""
+        return column_variants(self.prec, self.ny, self.kind == PST_C2C)
 
     def profile_enable(self, on: bool = True) -> None:
         check(lib.pst_profile_enable(self.handle, int(on)), "pst_profile_enable")
@@ -203,6 +210,16 @@ class Plan:
         s = C.c_int()
         check(lib.pst_sync_status(self.handle, C.byref(s)), "pst_sync_status")
         return s.value
+
+
+def column_variants(prec: int, n: int, single_field: bool) -> list:
+    """[(columns per block, values per thread, split)] by variant number."""
+    out = []
+    w, v, sp = C.c_int(), C.c_int(), C.c_int()
+    while lib.pst_column_variant_info(prec, n, len(out), int(single_field), C.byref(w), C.byref(v),
+                                      C.byref(sp)) == 0:
+        out.append((w.value, v.value, sp.value))
+    return out
 
 
 def make_params(eq: str, d, dt: float, g: float = 1.0, nu: float = 0.0, tol: float = 1e-10,

@@ -207,18 +207,23 @@ __host__ __device__ __forceinline__ void dft(cpx<T>* v) {
 // lds_idx(t + s*TL) = lds_idx(t) + s*TL + ((s*TL) >> 4) for t < TL.
 __host__ __device__ constexpr int lds_off(int x) { return x + (x >> 4); }
 
-// One Stockham stage for thread t; outputs either stay in registers (last
-// stage) or are scattered to the line's LDS buffer.
-template <int N, int S, bool INV, int WS, typename T>
-__host__ __device__ __forceinline__ void line_stage(cpx<T> (&v)[line_radix(N)], cpx<T>* lds, int t,
+// One Stockham stage for thread t.  A thread owns VPT values (VPT a
+// multiple of every stage radix; TL = N/VPT threads per line) and runs VPT/r
+// butterflies of the stage; outputs either stay in registers (last stage) or
+// go to the line's LDS slots.  SPLIT exchanges real parts, then imaginary
+// parts, through a buffer of scalars (half the LDS); the imaginary outputs
+// wait in the consumed input registers meanwhile.
+template <int N, int S, bool INV, int WS, int VPT, bool SPLIT, typename T>
+__host__ __device__ __forceinline__ void line_stage(cpx<T> (&v)[VPT], void* ldsv, int t,
                                                     const cpx<T>* __restrict__ tw) {
   constexpr int R = line_radix(N);
-  constexpr int TL = N / R;
+  constexpr int TL = N / VPT;
   constexpr int r = stage_radix(N, R, S);
   constexpr int Ns = stage_ns(N, R, S);
-  constexpr int B = R / r;
+  constexpr int B = VPT / r;
   constexpr bool last = (S == num_stages(N, R) - 1);
   constexpr int toff = stage_tw_offset(N, R, S);
+  static_assert(VPT % r == 0, "values per thread must be a multiple of each radix");
 #pragma unroll
   for (int b = 0; b < B; ++b) {
     const int j = t + b * TL;
@@ -240,44 +245,88 @@ __host__ __device__ __forceinline__ void line_stage(cpx<T> (&v)[line_radix(N)], 
       for (int q = 0; q < r; ++q) v[b + q * B] = w[q];
     } else {
       const int base = ((j / Ns) * Ns * r) + (j & (Ns - 1));
-      cpx<T>* pw = lds + lds_idx(base) * WS;
+      if constexpr (SPLIT) {
+        T* pw = static_cast<T*>(ldsv) + lds_idx(base) * WS;
 #pragma unroll
-      for (int q = 0; q < r; ++q) pw[lds_off(q * Ns) * WS] = w[q];
+        for (int q = 0; q < r; ++q) {
+          pw[lds_off(q * Ns) * WS] = w[q].re;
+          v[b + q * B].im = w[q].im;
+        }
+      } else {
+        cpx<T>* pw = static_cast<cpx<T>*>(ldsv) + lds_idx(base) * WS;
+#pragma unroll
+        for (int q = 0; q < r; ++q) pw[lds_off(q * Ns) * WS] = w[q];
+      }
     }
   }
 }
 
-template <int N, int S, bool INV, int WS, typename T>
-__host__ __device__ __forceinline__ void line_read(cpx<T> (&v)[line_radix(N)], const cpx<T>* lds, int t) {
+// Second half of a split exchange: the imaginary outputs parked in v[].im go
+// to the same slots the real parts used.
+template <int N, int S, int WS, int VPT, typename T>
+__host__ __device__ __forceinline__ void line_stage_im(const cpx<T> (&v)[VPT], T* lds, int t) {
   constexpr int R = line_radix(N);
-  constexpr int TL = N / R;
+  constexpr int TL = N / VPT;
+  constexpr int r = stage_radix(N, R, S);
+  constexpr int Ns = stage_ns(N, R, S);
+  constexpr int B = VPT / r;
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int j = t + b * TL;
+    const int base = ((j / Ns) * Ns * r) + (j & (Ns - 1));
+    T* pw = lds + lds_idx(base) * WS;
+#pragma unroll
+    for (int q = 0; q < r; ++q) pw[lds_off(q * Ns) * WS] = v[b + q * B].im;
+  }
+}
+
+template <int N, int WS, int VPT, typename T>
+__host__ __device__ __forceinline__ void line_read(cpx<T> (&v)[VPT], const cpx<T>* lds, int t) {
+  constexpr int TL = N / VPT;
   const cpx<T>* pr = lds + lds_idx(t) * WS;
 #pragma unroll
-  for (int s = 0; s < R; ++s) v[s] = pr[lds_off(s * TL) * WS];
+  for (int s = 0; s < VPT; ++s) v[s] = pr[lds_off(s * TL) * WS];
 }
 
-template <int N, int S, bool INV, int WS, typename T>
-__device__ __forceinline__ void line_stages(cpx<T> (&v)[line_radix(N)], cpx<T>* lds, int t,
-                                            const cpx<T>* __restrict__ tw) {
+template <int N, int WS, int VPT, bool IM, typename T>
+__host__ __device__ __forceinline__ void line_read_part(cpx<T> (&v)[VPT], const T* lds, int t) {
+  constexpr int TL = N / VPT;
+  const T* pr = lds + lds_idx(t) * WS;
+#pragma unroll
+  for (int s = 0; s < VPT; ++s) {
+    if constexpr (IM) v[s].im = pr[lds_off(s * TL) * WS];
+    else v[s].re = pr[lds_off(s * TL) * WS];
+  }
+}
+
+template <int N, int S, bool INV, int WS, int VPT, bool SPLIT, typename T>
+__device__ __forceinline__ void line_stages(cpx<T> (&v)[VPT], void* lds, int t, const cpx<T>* __restrict__ tw) {
   if constexpr (S < num_stages(N, line_radix(N))) {
-    line_stage<N, S, INV, WS>(v, lds, t, tw);
+    line_stage<N, S, INV, WS, VPT, SPLIT>(v, lds, t, tw);
     if constexpr (S < num_stages(N, line_radix(N)) - 1) {
       __syncthreads();
-      line_read<N, S, INV, WS>(v, lds, t);
+      if constexpr (SPLIT) {
+        line_read_part<N, WS, VPT, false>(v, static_cast<const T*>(lds), t);
+        __syncthreads();
+        line_stage_im<N, S, WS, VPT>(v, static_cast<T*>(lds), t);
+        __syncthreads();
+        line_read_part<N, WS, VPT, true>(v, static_cast<const T*>(lds), t);
+      } else {
+        line_read<N, WS, VPT>(v, static_cast<const cpx<T>*>(lds), t);
+      }
       __syncthreads();
-      line_stages<N, S + 1, INV, WS>(v, lds, t, tw);
+      line_stages<N, S + 1, INV, WS, VPT, SPLIT>(v, lds, t, tw);
     }
   }
 }
 
-// Full unnormalised FFT of a line whose N/R owners all call this together
+// Full unnormalised FFT of a line whose N/VPT owners all call this together
 // (every thread of the block must call it: it contains block barriers).
-// lds points at the line's first slot; WS is the slot stride (lines per
-// interleaved tile).
-template <int N, bool INV, int WS = 1, typename T>
-__device__ __forceinline__ void line_fft(cpx<T> (&v)[line_radix(N)], cpx<T>* lds, int t,
-                                         const cpx<T>* __restrict__ tw) {
-  line_stages<N, 0, INV, WS>(v, lds, t, tw);
+// lds points at the line's first slot (complex, or scalar when SPLIT); WS is
+// the slot stride (lines per interleaved tile).
+template <int N, bool INV, int WS = 1, int VPT = line_radix(N), bool SPLIT = false, typename T>
+__device__ __forceinline__ void line_fft(cpx<T> (&v)[VPT], void* lds, int t, const cpx<T>* __restrict__ tw) {
+  line_stages<N, 0, INV, WS, VPT, SPLIT>(v, lds, t, tw);
 }
 
 }  // namespace pst

@@ -132,7 +132,7 @@ static hipError_t cq_col(int ny, int nx, int nfields, void* spec, double* part, 
     ok = dispatch_w<T, N>(W, [&](auto wc) {
     constexpr int WT = decltype(wc)::value;
     using G = ColGeom<T, N, WT>;
-    const int tiles = (nx + W - 1) / W;
+    const int tiles = (nx + WT - 1) / WT;
     allow_lds((k_nls_cq_col<T, N, WT>), G::LDS_BYTES);
     hipLaunchKernelGGL((k_nls_cq_col<T, N, WT>), dim3(tiles * nfields), dim3(G::THREADS), G::LDS_BYTES,
                        s, (cpx<T>*)spec, nx, tiles, part, (const cpx<T>*)tw, kx0, ky0);

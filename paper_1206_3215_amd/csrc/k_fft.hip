@@ -29,27 +29,30 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_row_c2c(
 }
 
 // --------------------------------------------------------- C2C columns ---
-template <typename T, int N, bool INV, int WT>
-__global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_col_c2c(const cpx<T>* src, cpx<T>* dst, int ncols, int ld,
-                                                  int tiles_per_field, T scale,
-                                                  const cpx<T>* __restrict__ tw) {
-  using G = ColGeom<T, N, WT>;
+template <typename T, int N, bool INV, int WT, int VPT, bool SPLIT, int WPE>
+__global__ __launch_bounds__((WT * (N / VPT))) __attribute__((amdgpu_waves_per_eu(WPE))) void k_col_c2c(
+    const cpx<T>* src, cpx<T>* dst, int ncols, int ld, int tiles_per_field, T scale, const cpx<T>* __restrict__ tw) {
+  using G = ColGeom<T, N, WT, VPT, SPLIT>;
   extern __shared__ char smem[];
-  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
   const int c = threadIdx.x % WT, t = threadIdx.x / WT;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int field = tile / tiles_per_field;
+  const int fld = tile / tiles_per_field;
   const int col = (tile % tiles_per_field) * WT + c;
   const bool valid = col < ncols;
-  const size_t off = (size_t)field * N * ld + col;
-  cpx<T>* L = lds + c;
+  const int cc = valid ? col : ncols - 1;  // columns past the end recompute the last one, unstored
+  const size_t fbytes = (size_t)N * ld * sizeof(cpx<T>);
+  const FieldBuf in((const char*)src + fld * fbytes, (unsigned)fbytes);
+  const FieldBuf out((char*)dst + fld * fbytes, (unsigned)fbytes);
+  const unsigned o0 = (unsigned)(cc + t * ld) * (unsigned)sizeof(cpx<T>);
+  const unsigned ds = (unsigned)(G::TL * ld) * (unsigned)sizeof(cpx<T>);
+  void* L = SPLIT ? (void*)(reinterpret_cast<T*>(smem) + c) : (void*)(reinterpret_cast<cpx<T>*>(smem) + c);
   cpx<T> v[G::R];
 #pragma unroll
-  for (int s = 0; s < G::R; ++s) v[s] = valid ? src[off + (size_t)(t + s * G::TL) * ld] : cpx<T>{0, 0};
-  line_fft<N, INV, WT>(v, L, t, tw);
+  for (int s = 0; s < G::R; ++s) v[s] = in.template ldc<T>(o0, s * ds);
+  line_fft<N, INV, WT, VPT, SPLIT>(v, L, t, tw);
   if (valid) {
 #pragma unroll
-    for (int s = 0; s < G::R; ++s) dst[off + (size_t)(t + s * G::TL) * ld] = v[s] * scale;
+    for (int s = 0; s < G::R; ++s) out.st(o0, s * ds, v[s] * scale);
   }
 }
 
@@ -69,8 +72,8 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_row_r2c(
   cpx<T>* L = lds + lid * lds_line_stride<T>(N);
   cpx<T> v[G::R];
   const int ny = 1 << lny;
-  const T* ra = (const T*)in.at(la >> lny) + (size_t)(la & (ny - 1)) * N;
-  const T* rb = ra + N;
+  gptr<const T> ra = field<const T>(in, la >> lny) + (size_t)(la & (ny - 1)) * N;
+  gptr<const T> rb = ra + N;
 #pragma unroll
   for (int s = 0; s < G::R; ++s) {
     const int e = t + s * G::TL;
@@ -128,8 +131,8 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_row_c2r(
   }
   line_fft<N, true>(v, L, t, tw);
   const int ny = 1 << lny;
-  T* oa = (T*)out.at(la >> lny) + (size_t)(la & (ny - 1)) * N;
-  T* ob = oa + N;
+  gptr<T> oa = field<T>(out, la >> lny) + (size_t)(la & (ny - 1)) * N;
+  gptr<T> ob = oa + N;
 #pragma unroll
   for (int s = 0; s < G::R; ++s) {
     const int e = t + s * G::TL;
@@ -171,23 +174,15 @@ static hipError_t col_c2c(int ny, int ncols, int ld, int nfields, const void* sr
   bool ok = false;
   dispatch_n(ny, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    ok = dispatch_w<T, N>(W, [&](auto wc) {
-    constexpr int WT = decltype(wc)::value;
-    using G = ColGeom<T, N, WT>;
-    const int tiles = (ncols + W - 1) / W;
-    const int grid = tiles * nfields;
-    const size_t lds = G::LDS_BYTES;
-    if (inv) {
-      allow_lds((k_col_c2c<T, N, true, WT>), lds);
-      hipLaunchKernelGGL((k_col_c2c<T, N, true, WT>), dim3(grid), dim3(G::THREADS), lds, s,
-                         (const cpx<T>*)src, (cpx<T>*)dst, ncols, ld, tiles, (T)scale,
-                         (const cpx<T>*)tw);
-    } else {
-      allow_lds((k_col_c2c<T, N, false, WT>), lds);
-      hipLaunchKernelGGL((k_col_c2c<T, N, false, WT>), dim3(grid), dim3(G::THREADS), lds, s,
-                         (const cpx<T>*)src, (cpx<T>*)dst, ncols, ld, tiles, (T)scale,
-                         (const cpx<T>*)tw);
-    }
+    ok = dispatch_col1<T, N>(W, [&](auto cfg) {
+      using C = decltype(cfg);
+      using G = ColGeom<T, N, C::w, C::vpt, C::split>;
+      const int tiles = (ncols + C::w - 1) / C::w;
+      auto* k = inv ? &k_col_c2c<T, N, true, C::w, C::vpt, C::split, C::wpe>
+                    : &k_col_c2c<T, N, false, C::w, C::vpt, C::split, C::wpe>;
+      allow_lds(k, G::LDS_BYTES);
+      hipLaunchKernelGGL(k, dim3(tiles * nfields), dim3(G::THREADS), G::LDS_BYTES, s, (const cpx<T>*)src,
+                         (cpx<T>*)dst, ncols, ld, tiles, (T)scale, (const cpx<T>*)tw);
     });
   });
   return ok ? hipGetLastError() : hipErrorInvalidValue;
@@ -240,22 +235,27 @@ hipError_t fft_row_c2r(Prec p, int n, int nlines, int ny, const void* in, FieldR
                   : row_c2r<double>(n, nlines, ny, in, out, scale, tw, s);
 }
 
-int col_tile_max(Prec p, int n) {
-  int w = 0;
+bool col_variant_info(Prec p, int n, int var, bool single, int* w, int* vpt, int* split) {
+  bool found = false;
+  auto get = [&](auto cfg) {
+    using C = decltype(cfg);
+    *w = C::w;
+    *vpt = C::vpt;
+    *split = C::split ? 1 : 0;
+    found = true;
+  };
   dispatch_n(n, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    w = p == P32 ? ColTiles<float, N>::WMAX : ColTiles<double, N>::WMAX;
+    if (single) {
+      if (p == P32) dispatch_col1<float, N>(var, get);
+      else dispatch_col1<double, N>(var, get);
+    } else {
+      auto getw = [&](auto wc) { get(ColCfg<decltype(wc)::value, line_radix(N), false>{}); };
+      if (p == P32) dispatch_w<float, N>(var, getw);
+      else dispatch_w<double, N>(var, getw);
+    }
   });
-  return w;
-}
-
-int col_tile_alt(Prec p, int n) {
-  int w = 0;
-  dispatch_n(n, [&](auto nc) {
-    constexpr int N = decltype(nc)::value;
-    w = p == P32 ? ColTiles<float, N>::WALT : ColTiles<double, N>::WALT;
-  });
-  return w;
+  return found;
 }
 
 }  // namespace pst

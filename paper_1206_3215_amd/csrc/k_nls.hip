@@ -31,10 +31,10 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_nls_row(
   cpx<T>* L = lds + lid * lds_line_stride<T>(N);
   // lines past the end (a partial last block) recompute the last line and do not store
   const int lc = valid ? line : nlines - 1;
-  cpx<T>* g = (cpx<T>*)psi.at(lc >> lny) + (size_t)(lc & ((1 << lny) - 1)) * N;
+  gptr<cpx<T>> g = field<cpx<T>>(psi, lc >> lny) + (size_t)(lc & ((1 << lny) - 1)) * N;
   cpx<T> v[G::R];
 #pragma unroll
-  for (int s = 0; s < G::R; ++s) v[s] = g[t + s * G::TL];
+  for (int s = 0; s < G::R; ++s) v[s] = gload(g + (t + s * G::TL));
   if constexpr (MODE == 0) {
     line_fft<N, false>(v, L, t, tw);
 #pragma unroll
@@ -51,30 +51,33 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_nls_row(
   }
   if (valid) {
 #pragma unroll
-    for (int s = 0; s < G::R; ++s) g[t + s * G::TL] = v[s];
+    for (int s = 0; s < G::R; ++s) gstore(g + (t + s * G::TL), v[s]);
   }
 }
 
-template <typename T, int N, int WT>
-__global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_nls_col(FieldRef psi, int nx, int tiles_per_field,
-                                                  const cpx<T>* __restrict__ tw,
-                                                  const cpx<T>* __restrict__ ex,
-                                                  const cpx<T>* __restrict__ ey, T scale) {
-  using G = ColGeom<T, N, WT>;
+template <typename T, int N, int WT, int VPT, bool SPLIT, int WPE>
+__global__ __launch_bounds__((WT * (N / VPT))) __attribute__((amdgpu_waves_per_eu(WPE))) void k_nls_col(
+    FieldRef psi, int nx, int tiles_per_field, const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ ex,
+    const cpx<T>* __restrict__ ey, T scale) {
+  using G = ColGeom<T, N, WT, VPT, SPLIT>;
   extern __shared__ char smem[];
-  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
   const int c = threadIdx.x % WT, t = threadIdx.x / WT;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int field = tile / tiles_per_field;
+  const int fld = tile / tiles_per_field;
   const int col = (tile % tiles_per_field) * WT + c;
   const bool valid = col < nx;
   const int cc = valid ? col : nx - 1;  // columns past the end recompute the last one, unstored
-  cpx<T>* base = (cpx<T>*)psi.at(field) + cc;
-  cpx<T>* L = lds + c;
+  const FieldBuf fb(psi.at(fld), (unsigned)((size_t)N * nx * sizeof(cpx<T>)));
+  const unsigned o0 = (unsigned)(cc + t * nx) * (unsigned)sizeof(cpx<T>);
+  const unsigned ds = (unsigned)(G::TL * nx) * (unsigned)sizeof(cpx<T>);  // row step of value s
+  void* L = SPLIT ? (void*)(reinterpret_cast<T*>(smem) + c) : (void*)(reinterpret_cast<cpx<T>*>(smem) + c);
   cpx<T> v[G::R];
 #pragma unroll
-  for (int s = 0; s < G::R; ++s) v[s] = base[(size_t)(t + s * G::TL) * nx];
-  line_fft<N, false, WT>(v, L, t, tw);
+  for (int s = 0; s < G::R; ++s) v[s] = fb.template ldc<T>(o0, s * ds);
+  line_fft<N, false, WT, VPT, SPLIT>(v, L, t, tw);
+  // the propagator loads are issued after the forward transform: hoisted
+  // above it they would hold registers through the whole transform
+  asm volatile("" ::: "memory");
   const cpx<T> exm = ex[cc];
 #pragma unroll
   for (int s = 0; s < G::R; ++s) {
@@ -82,10 +85,10 @@ __global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_nls_col(FieldRef
     const cpx<T> wx = w + cmul(w, exm);
     v[s] = wx + cmul(wx, ey[t + s * G::TL]);
   }
-  line_fft<N, true, WT>(v, L, t, tw);
+  line_fft<N, true, WT, VPT, SPLIT>(v, L, t, tw);
   if (valid) {
 #pragma unroll
-    for (int s = 0; s < G::R; ++s) base[(size_t)(t + s * G::TL) * nx] = v[s];
+    for (int s = 0; s < G::R; ++s) fb.st(o0, s * ds, v[s]);
   }
 }
 
@@ -125,14 +128,14 @@ static hipError_t col(int ny, int nx, int nfields, FieldRef psi, const void* tw,
   bool ok = false;
   dispatch_n(ny, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    ok = dispatch_w<T, N>(W, [&](auto wc) {
-    constexpr int WT = decltype(wc)::value;
-    using G = ColGeom<T, N, WT>;
-    const int tiles = (nx + W - 1) / W;
-    allow_lds((k_nls_col<T, N, WT>), G::LDS_BYTES);
-    hipLaunchKernelGGL((k_nls_col<T, N, WT>), dim3(tiles * nfields), dim3(G::THREADS), G::LDS_BYTES, s,
-                       psi, nx, tiles, (const cpx<T>*)tw, (const cpx<T>*)ex,
-                       (const cpx<T>*)ey, (T)(1.0 / ((double)nx * N)));
+    ok = dispatch_col1<T, N>(W, [&](auto cfg) {
+      using C = decltype(cfg);
+      using G = ColGeom<T, N, C::w, C::vpt, C::split>;
+      const int tiles = (nx + C::w - 1) / C::w;
+      auto* k = &k_nls_col<T, N, C::w, C::vpt, C::split, C::wpe>;
+      allow_lds(k, G::LDS_BYTES);
+      hipLaunchKernelGGL(k, dim3(tiles * nfields), dim3(G::THREADS), G::LDS_BYTES, s, psi, nx, tiles,
+                         (const cpx<T>*)tw, (const cpx<T>*)ex, (const cpx<T>*)ey, (T)(1.0 / ((double)nx * N)));
     });
   });
   return ok ? hipGetLastError() : hipErrorInvalidValue;

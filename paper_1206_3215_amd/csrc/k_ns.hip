@@ -336,7 +336,7 @@ static hipError_t col(int mode, int ny, int nfields, const NsPtrs& P, const NsSc
     constexpr int WT = decltype(wc)::value;
     using G = ColGeom<T, N, WT>;
     const int ncols = S.nx / 2 + 1;
-    const int tiles = (ncols + Wt - 1) / Wt;
+    const int tiles = (ncols + WT - 1) / WT;
     NsColArgs a{S.kx0, S.ky0, S.hnu, S.qdt, S.nscale, S.dscale, S.nx, S.kx_cut, S.ky_cut};
     auto go = [&](auto kern) {
       allow_lds(kern, G::LDS_BYTES);
@@ -376,7 +376,7 @@ static hipError_t cqcol(int ny, int nx, int nfields, const void* XH, double* par
     ok = dispatch_w<T, N>(Wt, [&](auto wc) {
     constexpr int WT = decltype(wc)::value;
     using G = ColGeom<T, N, WT>;
-    const int tiles = (nx / 2 + 1 + Wt - 1) / Wt;
+    const int tiles = (nx / 2 + 1 + WT - 1) / WT;
     allow_lds(k_ns_cq_col<T, N, WT>, G::LDS_BYTES);
     hipLaunchKernelGGL((k_ns_cq_col<T, N, WT>), dim3(tiles * nfields), dim3(G::THREADS), G::LDS_BYTES, s,
                        (const cpx<T>*)XH, part, nx, tiles, kx0, ky0, (const cpx<T>*)tw);

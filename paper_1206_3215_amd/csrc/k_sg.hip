@@ -42,11 +42,11 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_row(
   // rows a, b are rows y, y+1 of field f; offsets are relative to each field
   const int f = la >> lny;
   const size_t ra = (size_t)(la & ((1 << lny) - 1)) * N, rb = ra + N;
-  const T* u_old = (const T*)u_old_f.at(f);
-  const T* d_old = (const T*)d_old_f.at(f);
-  T* u_out = (T*)u_out_f.at(f);
-  T* d_out = (T*)d_out_f.at(f);
-  T* prev_out = (T*)prev_out_f.at(f);
+  gptr<const T> u_old = field<const T>(u_old_f, f);
+  gptr<const T> d_old = field<const T>(d_old_f, f);
+  gptr<T> u_out = field<T>(u_out_f, f);
+  gptr<T> d_out = field<T>(d_out_f, f);
+  gptr<T> prev_out = field<T>(prev_out_f, f);
   cpx<T> u[G::R];
   if constexpr (MODE == SG_ENTRY) {
 #pragma unroll
@@ -273,7 +273,7 @@ static hipError_t col(int ny, int nx, int nfields, const void* U, const void* S,
     constexpr int WT = decltype(wc)::value;
     using G = ColGeom<T, N, WT>;
     const int ncols = nx / 2 + 1;
-    const int tiles = (ncols + Wt - 1) / Wt;
+    const int tiles = (ncols + WT - 1) / WT;
     allow_lds(k_sg_col<T, N, WT>, G::LDS_BYTES);
     hipLaunchKernelGGL((k_sg_col<T, N, WT>), dim3(tiles * nfields), dim3(G::THREADS), G::LDS_BYTES, s,
                        (const cpx<T>*)U, (const cpx<T>*)S, (cpx<T>*)W, ncols, tiles, (const cpx<T>*)tw,
@@ -320,7 +320,7 @@ static hipError_t hcol(int ny, int nx, int nfields, void* UB, double* part, cons
     constexpr int WT = decltype(wc)::value;
     using G = ColGeom<T, N, WT>;
     const int ncols = nx / 2 + 1;
-    const int tiles = (ncols + Wt - 1) / Wt;
+    const int tiles = (ncols + WT - 1) / WT;
     allow_lds(k_sg_h_col<T, N, WT>, G::LDS_BYTES);
     hipLaunchKernelGGL((k_sg_h_col<T, N, WT>), dim3(tiles * nfields), dim3(G::THREADS), G::LDS_BYTES, s,
                        (cpx<T>*)UB, part, ncols, nx, tiles, (const cpx<T>*)tw, kx0, ky0);

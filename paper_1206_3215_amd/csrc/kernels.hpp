@@ -35,18 +35,26 @@ struct RowGeom {
 
 // Column pass: W adjacent columns per block, thread (c, t) with c fastest so
 // that a wave reads W consecutive elements of a row per instruction; the W
-// lines are interleaved in LDS (slot * W + c).
-template <typename T, int N, int W>
+// lines are interleaved in LDS (slot * W + c).  VPT values per thread
+// (N/VPT threads per line); SPLIT exchanges real and imaginary parts one
+// after the other through half the LDS.
+template <typename T, int N, int W, int VPT = line_radix(N), bool SPLIT = false>
 struct ColGeom {
-  static constexpr int R = line_radix(N);
-  static constexpr int TL = N / R;
+  static constexpr int R = VPT;
+  static constexpr int TL = N / VPT;
   static constexpr int THREADS = W * TL;
-  static constexpr size_t LDS_BYTES = (size_t)W * lds_line_len(N) * sizeof(cpx<T>);
+  static constexpr size_t LDS_BYTES = (size_t)W * lds_line_len(N) * (SPLIT ? sizeof(T) : sizeof(cpx<T>));
 };
 
-// Column tiles compiled for a column length: the largest W with W*N/16 <=
-// 1024 threads, W <= 16 and <= 150 KB of LDS, and half of it.  The
-// autotuner chooses between the two.
+// Column tile variants compiled for a column length (the autotuner picks
+// one per plan).  Variant 0: the largest W with W*N/16 <= 1024 threads,
+// W <= 16 and <= 150 KB of LDS, 16 values per thread, complex exchange.
+// Single-field passes (NLS, C2C) of FP32 lines of 4096 and more, whose
+// variant-0 block fills a CU alone, add two variants that let two blocks
+// share a CU: 1, the same W with 32 values per thread and the split
+// exchange (half the threads and half the LDS); 2, the same W with 16
+// values per thread, the split exchange and registers capped for 8 waves
+// per SIMD.  Otherwise variant 1 is half of variant 0's W.
 template <typename T, int N>
 struct ColTiles {
   static constexpr int TL = N / line_radix(N);
@@ -55,22 +63,120 @@ struct ColTiles {
   }
   static constexpr int WMAX = fit(16) ? 16 : fit(8) ? 8 : fit(4) ? 4 : fit(2) ? 2 : 1;
   static constexpr int WALT = WMAX > 1 ? WMAX / 2 : 1;
+  static constexpr bool SPLIT1 = std::is_same<T, float>::value && N >= 4096;
 };
 
-// Calls f(IntC<W>) for the compiled tile equal to w (false if none).
+// W columns per block, VPT values per thread, split exchange, and the
+// minimum waves per SIMD the register allocation must allow (1: no cap).
+template <int W, int VPT, bool SPLIT, int WPE = 1>
+struct ColCfg {
+  static constexpr int w = W, vpt = VPT, wpe = WPE;
+  static constexpr bool split = SPLIT;
+};
+
+// Calls f(ColCfg<...>) for variant `var` of a single-field column pass.
 template <typename T, int N, class F>
-bool dispatch_w(int w, F&& f) {
+bool dispatch_col1(int var, F&& f) {
   using CT = ColTiles<T, N>;
-  if (w == CT::WMAX) {
+  constexpr int R = line_radix(N);
+  if (var == 0) {
+    f(ColCfg<CT::WMAX, R, false>{});
+    return true;
+  }
+  if constexpr (CT::SPLIT1) {
+    if (var == 1) {
+      f(ColCfg<CT::WMAX, 32, true>{});
+      return true;
+    }
+    if (var == 2) {
+      f(ColCfg<CT::WMAX, R, true, 8>{});
+      return true;
+    }
+  } else if (var == 1) {
+    f(ColCfg<CT::WALT, R, false>{});
+    return true;
+  }
+  return false;
+}
+
+// Calls f(IntC<W>) for variant `var` of a two-line column pass.
+template <typename T, int N, class F>
+bool dispatch_w(int var, F&& f) {
+  using CT = ColTiles<T, N>;
+  if (var == 0) {
     f(std::integral_constant<int, CT::WMAX>{});
     return true;
   }
-  if (w == CT::WALT) {
+  if (var == 1) {
     f(std::integral_constant<int, CT::WALT>{});
     return true;
   }
   return false;
 }
+
+// Pointer into the global address space.  Fields reached through a
+// FieldRef (base + stride or a device pointer table) are plain pointers to
+// the compiler; accessing them through gptr makes it emit global (not flat)
+// memory instructions, which do not share the LDS wait counter.
+template <typename P>
+using gptr = __attribute__((address_space(1))) P*;
+template <typename P>
+__device__ __forceinline__ gptr<P> field(const FieldRef& f, int i) {
+  return (gptr<P>)f.at(i);
+}
+// Load and store of a complex value through a global pointer (one 8- or
+// 16-byte access each).
+template <typename T>
+__device__ __forceinline__ cpx<T> gload(gptr<const cpx<T>> p) {
+  using V = T __attribute__((ext_vector_type(2)));
+  const V a = *(gptr<const V>)p;
+  return {a.x, a.y};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> gload(gptr<cpx<T>> p) {
+  return gload((gptr<const cpx<T>>)p);
+}
+template <typename T>
+__device__ __forceinline__ void gstore(gptr<cpx<T>> p, cpx<T> v) {
+  using V = T __attribute__((ext_vector_type(2)));
+  *(gptr<V>)p = V{v.re, v.im};
+}
+
+// Buffer-resource access to one field (at most 2 GiB): 32-bit byte offsets,
+// a per-lane part (voff) and a wave-uniform part (soff, kept in a scalar
+// register), so a thread's many strided accesses cost no 64-bit address
+// registers.  Word 3 of the descriptor is the gfx9 raw-buffer format.
+struct FieldBuf {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ FieldBuf(const void* base, unsigned bytes)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000)) {}
+  __device__ __forceinline__ cpx<float> ld(cpx<float>*, unsigned voff, unsigned soff) const {
+    using V = float __attribute__((ext_vector_type(2)));
+    const V a = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    return {a.x, a.y};
+  }
+  __device__ __forceinline__ cpx<double> ld(cpx<double>*, unsigned voff, unsigned soff) const {
+    using V = double __attribute__((ext_vector_type(2)));
+    const V a = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    return {a.x, a.y};
+  }
+  __device__ __forceinline__ void st(unsigned voff, unsigned soff, cpx<float> v) const {
+    using V = float __attribute__((ext_vector_type(2)));
+    using U = unsigned long long __attribute__((ext_vector_type(1)));
+    const V a = {v.re, v.im};
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, a), r, voff, soff, 0);
+  }
+  __device__ __forceinline__ void st(unsigned voff, unsigned soff, cpx<double> v) const {
+    using V = double __attribute__((ext_vector_type(2)));
+    using U = unsigned __attribute__((ext_vector_type(4)));
+    const V a = {v.re, v.im};
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, a), r, voff, soff, 0);
+  }
+  template <typename T>
+  __device__ __forceinline__ cpx<T> ldc(unsigned voff, unsigned soff) const {
+    return ld((cpx<T>*)nullptr, voff, soff);
+  }
+};
 
 // Blocks are handed to the 8 XCDs of the chip round robin (block b runs on
 // XCD b mod 8).  Give each XCD a contiguous range of tiles, so that the

@@ -32,8 +32,10 @@ enum : int { ST_NONFINITE = 1, ST_NOT_CONVERGED = 2 };
 
 // Column-pass tiles compiled for length n: the widest (W columns per block,
 // bounded by the block size and the LDS footprint) and its half.
-int col_tile_max(Prec p, int n);
-int col_tile_alt(Prec p, int n);
+// Column tile variant `var` for lines of length n: columns per block,
+// values per thread, split exchange.  single: a single-field pass (NLS,
+// C2C); two-line passes have no split variants.  False if not compiled.
+bool col_variant_info(Prec p, int n, int var, bool single, int* w, int* vpt, int* split);
 
 // ----------------------------------------------------------------- FFT ---
 // Row pass over nlines contiguous complex lines of length n: out = FFT(in)

@@ -232,7 +232,6 @@ pst_status fft2d_plan(int nx, int ny, pst_kind kind, pst_prec prec, int batch, v
   pl->csize = prec == PST_FP32 ? 8 : 16;
   pl->rsize = prec == PST_FP32 ? 4 : 8;
   pl->P = prec == PST_FP32 ? P32 : P64;
-  pl->Wcol = col_tile_max(pl->P, ny);
   pst_status st = hip_check(hipGetDevice(&pl->device), "hipGetDevice");
   if (st == PST_OK) st = upload_complex(pl, twiddles(nx), &pl->tw_x, true, 1.0);
   if (st == PST_OK) st = upload_complex(pl, twiddles(ny), &pl->tw_y, true, 1.0);
@@ -297,7 +296,7 @@ pst_status fft2d_exec(pst_plan pl, const void* in, void* out, int sign) {
   if (pl->kind == PST_C2C) {
     st = hip_check(fft_row_c2c(pl->P, nx, B * ny, in, out, inv, 1.0, pl->tw_x, pl->stream), "row pass");
     if (st != PST_OK) return st;
-    return hip_check(fft_col_c2c(pl->P, ny, nx, nx, B, out, out, inv, sc, pl->tw_y, pl->Wcol, pl->stream),
+    return hip_check(fft_col_c2c(pl->P, ny, nx, nx, B, out, out, inv, sc, pl->tw_y, pl->colvar, pl->stream),
                      "column pass");
   }
   if (in == out) return fail(PST_ERR_INVALID, "R2C transforms cannot run in place");
@@ -319,12 +318,23 @@ pst_status fft2d_exec(pst_plan pl, const void* in, void* out, int sign) {
                    "c2r row pass");
 }
 
-pst_status pst_set_column_tile(pst_plan pl, int w) {
+pst_status pst_set_column_variant(pst_plan pl, int variant) {
   if (pl == nullptr) return fail(PST_ERR_INVALID, "plan is NULL");
-  if (w != col_tile_max(pl->P, pl->ny) && w != col_tile_alt(pl->P, pl->ny))
-    return fail(PST_ERR_INVALID, "column tile %d is not compiled for ny=%d (use %d or %d)", w, pl->ny,
-                col_tile_max(pl->P, pl->ny), col_tile_alt(pl->P, pl->ny));
-  pl->Wcol = w;
+  int w, v, sp;
+  if (!col_variant_info(pl->P, pl->ny, variant, pl->kind == PST_C2C, &w, &v, &sp))
+    return fail(PST_ERR_INVALID, "column variant %d is not compiled for ny=%d", variant, pl->ny);
+  pl->colvar = variant;
+  return PST_OK;
+}
+
+pst_status pst_column_variant_info(pst_prec prec, int n, int variant, int single_field, int* columns,
+                                   int* values_per_thread, int* split) {
+  if (prec != PST_FP32 && prec != PST_FP64) return fail(PST_ERR_INVALID, "unknown precision %d", (int)prec);
+  if (columns == nullptr || values_per_thread == nullptr || split == nullptr)
+    return fail(PST_ERR_INVALID, "output pointer is NULL");
+  if (!col_variant_info(prec == PST_FP32 ? P32 : P64, n, variant, single_field != 0, columns, values_per_thread,
+                        split))
+    return fail(PST_ERR_INVALID, "no column variant %d for length %d", variant, n);
   return PST_OK;
 }
 

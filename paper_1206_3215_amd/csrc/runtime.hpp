@@ -28,7 +28,7 @@ struct pst_plan_s {
   hipStream_t stream = nullptr;
   int device = 0;
   size_t csize = 8, rsize = 4;  // bytes per complex / real element
-  int Wcol = 1;                 // column tile (columns per block) for length ny
+  int colvar = 0;               // column tile variant for length ny
   void* tw_x = nullptr;         // twiddles of the x lines (length nx)
   void* tw_y = nullptr;         // twiddles of the y lines (length ny)
   int* dstatus = nullptr;       // latched device status bits
@@ -67,6 +67,6 @@ void prof_begin(Plan* pl, int pass);
 void prof_end(Plan* pl);
 
 inline void* ws_at(Plan* pl, size_t off) { return static_cast<char*>(pl->ws) + off; }
-inline int col_w(Plan* pl, int n) { return n == pl->ny ? pl->Wcol : col_tile_max(pl->P, n); }
+inline int col_w(Plan* pl, int n) { return n == pl->ny ? pl->colvar : 0; }
 
 }  // namespace pst

@@ -77,7 +77,7 @@ static pst_status nls_check(Plan* pl, const pst_nls_params* p, int nsteps) {
 static pst_status nls_run(Plan* pl, FieldRef psi, const pst_nls_params* p, int nsteps) {
   if (nsteps == 0) return PST_OK;
   TRY(nls_tables(pl, p));
-  const int nx = pl->nx, ny = pl->ny, B = pl->batch, W = pl->Wcol;
+  const int nx = pl->nx, ny = pl->ny, B = pl->batch, W = pl->colvar;
   const int lines = B * ny;
   const double pc = p->g * p->dt / ((double)nx * nx);
   const NlsTables& t = pl->nls;
@@ -130,7 +130,7 @@ pst_status conserved_quantities(pst_plan pl, pst_eq eq, const void* f0, const vo
     const double kin = 0.5 * p->d.lx * p->d.ly / ((double)nx * ny * (double)nx * ny);
     TRY(hip_check(nls_cq_row(pl->P, nx, B * ny, f0, spec, rowp, pl->tw_x, s), "cq row"));
     TRY(hip_check(nls_cq_col(pl->P, ny, nx, B, spec, colp, pl->tw_y, 2 * M_PI / p->d.lx,
-                             2 * M_PI / p->d.ly, pl->Wcol, s),
+                             2 * M_PI / p->d.ly, 0, s),
                   "cq column"));
     TRY(hip_check(nls_cq_finish(B, ny, nx, rowp, colp, dxdy, kin, p->g, pl->dres, pl->dstatus, s), "cq finish"));
   } else if (eq == PST_SG) {
@@ -376,7 +376,7 @@ pst_status ns_step(pst_plan pl, void* omega, const pst_ns_params* p, int nsteps,
 extern "C" pst_status pst_autotune(pst_plan pl, pst_eq eq, int* chosen);
 namespace {
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int>, int> g_tuned;  // (eq, prec, nx, ny) -> tile
+std::map<std::tuple<int, int, int, int>, int> g_tuned;  // (eq, prec, nx, ny) -> variant
 }  // namespace
 
 // ptab: zeroed propagator stand-in of max(nx, ny) complex entries.
@@ -428,8 +428,8 @@ extern "C" pst_status pst_autotune(pst_plan pl, pst_eq eq, int* chosen) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) {
-      pl->Wcol = it->second;
-      if (chosen) *chosen = pl->Wcol;
+      pl->colvar = it->second;
+      if (chosen) *chosen = pl->colvar;
       return PST_OK;
     }
   }
@@ -440,19 +440,18 @@ extern "C" pst_status pst_autotune(pst_plan pl, pst_eq eq, int* chosen) {
   TRY(hip_check(hipMalloc(&ptab, pbytes), "hipMalloc(autotune table)"));
   pl->owned.push_back(ptab);
   TRY(hip_check(hipMemsetAsync(ptab, 0, pbytes, pl->stream), "clear autotune table"));
-  const int cand[2] = {col_tile_max(pl->P, pl->ny), col_tile_alt(pl->P, pl->ny)};
-  int best = cand[0];
+  int best = 0;
   float best_ms = 1e30f;
-  for (int i = 0; i < 2; ++i) {
-    if (i == 1 && cand[1] == cand[0]) break;
+  int w, q, sp;
+  for (int v = 0; col_variant_info(pl->P, pl->ny, v, eq == PST_NLS, &w, &q, &sp); ++v) {
     float ms = 0.f;
-    TRY(time_col(pl, eq, cand[i], ptab, &ms));
+    TRY(time_col(pl, eq, v, ptab, &ms));
     if (ms < best_ms) {
       best_ms = ms;
-      best = cand[i];
+      best = v;
     }
   }
-  pl->Wcol = best;
+  pl->colvar = best;
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tuned[key] = best;
