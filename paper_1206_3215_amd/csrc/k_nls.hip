@@ -19,39 +19,59 @@
 
 namespace pst {
 
-template <typename T, int N, int MODE>
-__global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_nls_row(
+// UNI: all lines of a block lie in one field (always so when the field has
+// at least LPB rows); the field is then reached through a buffer resource.
+template <typename T, int N, int MODE, int VPT, bool SPLIT, bool UNI>
+__global__ __launch_bounds__((RowGeom<T, N, VPT, SPLIT>::THREADS)) void k_nls_row(
     FieldRef psi, int nlines, int lny, T phase_coef, T scale, const cpx<T>* __restrict__ tw) {
-  using G = RowGeom<T, N>;
+  using G = RowGeom<T, N, VPT, SPLIT>;
   extern __shared__ char smem[];
-  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
   const int lid = threadIdx.x / G::TL, t = threadIdx.x % G::TL;
   const int line = blockIdx.x * G::LPB + lid;
   const bool valid = line < nlines;
-  cpx<T>* L = lds + lid * lds_line_stride<T>(N);
+  void* L = SPLIT ? (void*)(reinterpret_cast<T*>(smem) + lid * G::STRIDE)
+                  : (void*)(reinterpret_cast<cpx<T>*>(smem) + lid * G::STRIDE);
   // lines past the end (a partial last block) recompute the last line and do not store
   const int lc = valid ? line : nlines - 1;
-  gptr<cpx<T>> g = field<cpx<T>>(psi, lc >> lny) + (size_t)(lc & ((1 << lny) - 1)) * N;
+  const int ny = 1 << lny;
   cpx<T> v[G::R];
+  auto body = [&]() {
+    if constexpr (MODE == 0) {
+      line_fft<N, false, 1, VPT, SPLIT>(v, L, t, tw);
 #pragma unroll
-  for (int s = 0; s < G::R; ++s) v[s] = gload(g + (t + s * G::TL));
-  if constexpr (MODE == 0) {
-    line_fft<N, false>(v, L, t, tw);
+      for (int s = 0; s < G::R; ++s) v[s] = v[s] * scale;
+    } else if constexpr (MODE == 1) {
+      line_fft<N, true, 1, VPT, SPLIT>(v, L, t, tw);
 #pragma unroll
-    for (int s = 0; s < G::R; ++s) v[s] = v[s] * scale;
-  } else if constexpr (MODE == 1) {
-    line_fft<N, true>(v, L, t, tw);
+      for (int s = 0; s < G::R; ++s) v[s] = rotate_neg(v[s], phase_coef * norm2(v[s]));
+      line_fft<N, false, 1, VPT, SPLIT>(v, L, t, tw);
+    } else {
+      line_fft<N, true, 1, VPT, SPLIT>(v, L, t, tw);
 #pragma unroll
-    for (int s = 0; s < G::R; ++s) v[s] = rotate_neg(v[s], phase_coef * norm2(v[s]));
-    line_fft<N, false>(v, L, t, tw);
+      for (int s = 0; s < G::R; ++s) v[s] = v[s] * scale;
+    }
+  };
+  if constexpr (UNI) {
+    const int f = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * G::LPB) >> lny);
+    const FieldBuf fb(psi.at(f), (unsigned)((size_t)ny * N * sizeof(cpx<T>)));
+    const unsigned o0 = (unsigned)((lc & (ny - 1)) * N + t) * (unsigned)sizeof(cpx<T>);
+    constexpr unsigned ds = G::TL * sizeof(cpx<T>);
+#pragma unroll
+    for (int s = 0; s < G::R; ++s) v[s] = fb.template ldc<T>(o0, s * ds);
+    body();
+    if (valid) {
+#pragma unroll
+      for (int s = 0; s < G::R; ++s) fb.st(o0, s * ds, v[s]);
+    }
   } else {
-    line_fft<N, true>(v, L, t, tw);
+    gptr<cpx<T>> g = field<cpx<T>>(psi, lc >> lny) + (size_t)(lc & (ny - 1)) * N;
 #pragma unroll
-    for (int s = 0; s < G::R; ++s) v[s] = v[s] * scale;
-  }
-  if (valid) {
+    for (int s = 0; s < G::R; ++s) v[s] = gload(g + (t + s * G::TL));
+    body();
+    if (valid) {
 #pragma unroll
-    for (int s = 0; s < G::R; ++s) gstore(g + (t + s * G::TL), v[s]);
+      for (int s = 0; s < G::R; ++s) gstore(g + (t + s * G::TL), v[s]);
+    }
   }
 }
 
@@ -92,26 +112,42 @@ __global__ __launch_bounds__((WT * (N / VPT))) __attribute__((amdgpu_waves_per_e
   }
 }
 
+// Row configuration: 32 values per thread with the split exchange for FP32
+// lines of 8192 (256 threads and 35 KB of LDS per line, so several lines
+// share a CU); 16 values per thread and the complex exchange otherwise.
+template <typename T, int N>
+struct NlsRowCfg {
+  static constexpr bool BIG = std::is_same<T, float>::value && N >= 8192;
+  static constexpr int VPT = BIG ? 32 : line_radix(N);
+  static constexpr bool SPLIT = BIG;
+};
+
+template <typename T, int N, int MODE, bool UNI>
+static void launch_row(int nlines, int ny, FieldRef psi, double pc, double scale, const void* tw, hipStream_t s) {
+  using C = NlsRowCfg<T, N>;
+  using G = RowGeom<T, N, C::VPT, C::SPLIT>;
+  auto* k = &k_nls_row<T, N, MODE, C::VPT, C::SPLIT, UNI>;
+  allow_lds(k, G::LDS_BYTES);
+  hipLaunchKernelGGL(k, dim3((nlines + G::LPB - 1) / G::LPB), dim3(G::THREADS), G::LDS_BYTES, s, psi, nlines,
+                     ilog2c(ny), (T)pc, (T)scale, (const cpx<T>*)tw);
+}
+
 template <typename T>
 static hipError_t row(int nx, int nlines, int ny, FieldRef psi, int mode, double pc, double scale,
                       const void* tw, hipStream_t s) {
   bool ok = dispatch_n(nx, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    using G = RowGeom<T, N>;
-    const int grid = (nlines + G::LPB - 1) / G::LPB;
-    if (mode == 0) {
-      allow_lds((k_nls_row<T, N, 0>), G::LDS_BYTES);
-      hipLaunchKernelGGL((k_nls_row<T, N, 0>), dim3(grid), dim3(G::THREADS), G::LDS_BYTES, s,
-                         psi, nlines, ilog2c(ny), (T)pc, (T)scale, (const cpx<T>*)tw);
-    } else if (mode == 1) {
-      allow_lds((k_nls_row<T, N, 1>), G::LDS_BYTES);
-      hipLaunchKernelGGL((k_nls_row<T, N, 1>), dim3(grid), dim3(G::THREADS), G::LDS_BYTES, s,
-                         psi, nlines, ilog2c(ny), (T)pc, (T)scale, (const cpx<T>*)tw);
-    } else {
-      allow_lds((k_nls_row<T, N, 2>), G::LDS_BYTES);
-      hipLaunchKernelGGL((k_nls_row<T, N, 2>), dim3(grid), dim3(G::THREADS), G::LDS_BYTES, s,
-                         psi, nlines, ilog2c(ny), (T)pc, (T)scale, (const cpx<T>*)tw);
-    }
+    using C = NlsRowCfg<T, N>;
+    constexpr int LPB = RowGeom<T, N, C::VPT, C::SPLIT>::LPB;
+    const bool uni = LPB == 1 || ny >= LPB;
+    auto go = [&](auto m) {
+      constexpr int MODE = decltype(m)::value;
+      if (uni) launch_row<T, N, MODE, true>(nlines, ny, psi, pc, scale, tw, s);
+      else launch_row<T, N, MODE, false>(nlines, ny, psi, pc, scale, tw, s);
+    };
+    if (mode == 0) go(IntC<0>{});
+    else if (mode == 1) go(IntC<1>{});
+    else go(IntC<2>{});
   });
   return ok ? hipGetLastError() : hipErrorInvalidValue;
 }

@@ -22,15 +22,17 @@ __host__ __device__ constexpr int lds_line_stride(int N) {
   return N + N / 16 + (int)(128 / sizeof(cpx<T>));
 }
 
-// Row pass: LPB lines per block, N/R threads per line, >= 256 threads per
-// block when the line is short.
-template <typename T, int N>
+// Row pass: LPB lines per block, N/VPT threads per line, >= 256 threads
+// per block when the line is short.  SPLIT exchanges real and imaginary
+// parts one after the other through half the LDS.
+template <typename T, int N, int VPT = line_radix(N), bool SPLIT = false>
 struct RowGeom {
-  static constexpr int R = line_radix(N);
-  static constexpr int TL = N / R;
+  static constexpr int R = VPT;
+  static constexpr int TL = N / VPT;
   static constexpr int LPB = TL >= 256 ? 1 : 256 / TL;
   static constexpr int THREADS = LPB * TL;
-  static constexpr size_t LDS_BYTES = (size_t)LPB * lds_line_stride<T>(N) * sizeof(cpx<T>);
+  static constexpr int STRIDE = SPLIT ? N + N / 16 + (int)(128 / sizeof(T)) : lds_line_stride<T>(N);
+  static constexpr size_t LDS_BYTES = (size_t)LPB * STRIDE * (SPLIT ? sizeof(T) : sizeof(cpx<T>));
 };
 
 // Column pass: W adjacent columns per block, thread (c, t) with c fastest so

@@ -14,12 +14,13 @@ pytestmark = pytest.mark.gpu
 TOL = {0: 1e-4, 1: 1e-11}
 
 
-def run_gpu(psi0, d, dt, g, nsteps, prec, chunk=None, diag=False):
+def run_gpu(psi0, d, dt, g, nsteps, prec, chunk=None, diag=False, variant=0):
     torch = need_gpu()
     from paper_1206_3215_amd import binding as b
     batch = psi0.shape[0] if psi0.ndim == 3 else 1
     ny, nx = psi0.shape[-2:]
     plan = b.Plan(nx, ny, b.PST_C2C, prec, batch)
+    plan.set_column_variant(variant)
     psi = to_dev(psi0.reshape(batch, ny, nx), torch, plan.complex_dtype)
     diags = []
     chunk = chunk or nsteps
@@ -91,14 +92,36 @@ def test_plane_wave_closed_form_full_size(prec):
     assert rel_err(got, exact) < TOL[prec]
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_headline_size_against_oracle_short(prec):
-    # 4096^2 on [-5pi,5pi)^2, the benchmark's launch configuration, 10 steps.
+@pytest.fixture(scope="module")
+def oracle_4096_10():
     d = inputs.PAPER_DOMAIN
     psi0 = inputs.nls_gaussian(4096, 4096, d, seed=0)
     ref, _ = onls.run(psi0, d.lx, d.ly, 1e-3, 1.0, 10)
-    got, _ = run_gpu(psi0, d, 1e-3, 1.0, 10, prec)
+    return psi0, ref
+
+
+@pytest.mark.parametrize("prec,variant", [(0, 0), (0, 1), (0, 2), (1, 0), (1, 1)])
+def test_headline_size_against_oracle_short(prec, variant, oracle_4096_10):
+    # 4096^2 on [-5pi,5pi)^2, 10 steps, in every column variant (the
+    # benchmark runs the one the autotuner picks).
+    d = inputs.PAPER_DOMAIN
+    psi0, ref = oracle_4096_10
+    got, _ = run_gpu(psi0, d, 1e-3, 1.0, 10, prec, variant=variant)
     assert rel_err(got, ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_plane_wave_closed_form_8192(prec):
+    # the largest compiled line length (32 values per thread and the split
+    # exchange in FP32 rows and columns)
+    n, L, A, dt, steps = 8192, 10 * math.pi, 0.3, 1e-3, 20
+    X, Y = inputs.grid(n, n, inputs.Domain(L, L, 0, 0))
+    k = 2 * math.pi * np.array([-7, 4]) / L
+    psi0 = A * np.exp(1j * (k[0] * X + k[1] * Y))
+    variant = 1 if prec == 0 else 0
+    got, _ = run_gpu(psi0, inputs.Domain(L, L, 0, 0), dt, 1.0, steps, prec, variant=variant)
+    exact = psi0 * np.exp(-1j * (k @ k + A * A) * dt * steps)
+    assert rel_err(got, exact) < TOL[prec]
 
 
 @pytest.fixture(scope="module")
