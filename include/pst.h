@@ -212,7 +212,9 @@ const char* pst_version(void);
  *   1: the same W, 32 values per thread, real and imaginary parts exchanged
  *      one after the other (half the threads and half the LDS per block);
  *   2: the same W, 16 values per thread, the split exchange, registers
- *      capped so that two 1024-thread blocks fit a CU.
+ *      capped so that two 1024-thread blocks fit a CU;
+ *   3: twice the W, 32 values per thread, the split exchange (wider row
+ *      segments per block, one block per CU).
  * For every other pass and length, variant 1 is half of variant 0's W.
  * pst_column_variant_info reports (columns per block, values per thread,
  * split exchange 0/1) of variant for length n; single_field != 0 asks about

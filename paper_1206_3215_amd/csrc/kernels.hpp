@@ -56,7 +56,9 @@ struct ColGeom {
 // share a CU: 1, the same W with 32 values per thread and the split
 // exchange (half the threads and half the LDS); 2, the same W with 16
 // values per thread, the split exchange and registers capped for 8 waves
-// per SIMD.  Otherwise variant 1 is half of variant 0's W.
+// per SIMD; and one that widens the row segments a block reads and writes:
+// 3, twice the W with 32 values per thread and the split exchange (variant
+// 0's threads and LDS).  Otherwise variant 1 is half of variant 0's W.
 template <typename T, int N>
 struct ColTiles {
   static constexpr int TL = N / line_radix(N);
@@ -92,6 +94,10 @@ bool dispatch_col1(int var, F&& f) {
     }
     if (var == 2) {
       f(ColCfg<CT::WMAX, R, true, 8>{});
+      return true;
+    }
+    if (var == 3) {
+      f(ColCfg<2 * CT::WMAX, 32, true>{});
       return true;
     }
   } else if (var == 1) {

@@ -88,7 +88,7 @@ def test_column_variants_agree(prec, n, batch):
     plan = b.Plan(n, n, b.PST_C2C, prec, batch)
     variants = plan.column_variants()
     if prec == b.PST_FP32 and n >= 4096:
-        assert len(variants) == 3 and variants[1][1] == 32 and variants[1][2] == 1
+        assert len(variants) == 4 and variants[1][1] == 32 and variants[1][2] == 1
     ref = None
     for v, (_, vpt, _) in enumerate(variants):
         plan.set_column_variant(v)

@@ -100,7 +100,7 @@ def oracle_4096_10():
     return psi0, ref
 
 
-@pytest.mark.parametrize("prec,variant", [(0, 0), (0, 1), (0, 2), (1, 0), (1, 1)])
+@pytest.mark.parametrize("prec,variant", [(0, 0), (0, 1), (0, 2), (0, 3), (1, 0), (1, 1)])
 def test_headline_size_against_oracle_short(prec, variant, oracle_4096_10):
     # 4096^2 on [-5pi,5pi)^2, 10 steps, in every column variant (the
     # benchmark runs the one the autotuner picks).
