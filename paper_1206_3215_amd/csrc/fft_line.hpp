@@ -207,6 +207,34 @@ __host__ __device__ __forceinline__ void dft(cpx<T>* v) {
 // lds_idx(t + s*TL) = lds_idx(t) + s*TL + ((s*TL) >> 4) for t < TL.
 __host__ __device__ constexpr int lds_off(int x) { return x + (x >> 4); }
 
+// Twiddle load: entry `idx` of a line length's table of `len` entries.  On
+// the device it goes through a buffer resource with the stage/radix part of
+// the index as a wave-uniform scalar offset, so a thread's twiddle
+// addresses cost one register per stage instead of a 64-bit address per
+// entry (which the compiler would otherwise keep live across every
+// transform of a kernel).
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> tw_load(const cpx<T>* tw, int len, unsigned k, unsigned base) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<cpx<T>*>(tw), 0, len * (int)sizeof(cpx<T>), 0x00020000);
+  if constexpr (sizeof(T) == 4) {
+    using V = float __attribute__((ext_vector_type(2)));
+    const V a = __builtin_bit_cast(
+        V, __builtin_amdgcn_raw_buffer_load_b64(r, k * (unsigned)sizeof(cpx<T>), base * (unsigned)sizeof(cpx<T>), 0));
+    return {a.x, a.y};
+  } else {
+    using V = double __attribute__((ext_vector_type(2)));
+    const V a = __builtin_bit_cast(
+        V, __builtin_amdgcn_raw_buffer_load_b128(r, k * (unsigned)sizeof(cpx<T>), base * (unsigned)sizeof(cpx<T>), 0));
+    return {a.x, a.y};
+  }
+#else
+  (void)len;
+  return tw[base + k];
+#endif
+}
+
 // One Stockham stage for thread t.  A thread owns VPT values (VPT a
 // multiple of every stage radix; TL = N/VPT threads per line) and runs VPT/r
 // butterflies of the stage; outputs either stay in registers (last stage) or
@@ -234,8 +262,8 @@ __host__ __device__ __forceinline__ void line_stage(cpx<T> (&v)[VPT], void* ldsv
       const unsigned k = (unsigned)j & (Ns - 1);
 #pragma unroll
       for (int q = 1; q < r; ++q) {
-        const cpx<T>* twq = tw + (toff + (q - 1) * Ns);  // uniform base, per-lane offset k
-        const cpx<T> c = twq[k];
+        // uniform base toff + (q-1) Ns, per-lane offset k
+        const cpx<T> c = tw_load(tw, twiddle_table_len(N), k, (unsigned)(toff + (q - 1) * Ns));
         w[q] = INV ? cmul_conj(w[q], c) : cmul(w[q], c);
       }
     }

@@ -52,27 +52,35 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_ns_row(
     if (fields_done(done, (2 * p0) / ny, l1 / ny)) return;
   }
   cpx<T>* L = lds + lid * lds_line_stride<T>(N);
-  const size_t oa = (size_t)la * H, ob = (size_t)lb * H;
+  // the block's rows through buffers (first row 2 p0, 2 LPB rows)
+  const int r0 = 2 * blockIdx.x * G::LPB;
+  const FieldBuf d0 = pair_rows<T, N>(D, r0, 2 * G::LPB), d1 = pair_rows<T, N>(D + dstride, r0, 2 * G::LPB),
+                 d2 = pair_rows<T, N>(D + 2 * dstride, r0, 2 * G::LPB),
+                 d3 = pair_rows<T, N>(D + 3 * dstride, r0, 2 * G::LPB), nh = pair_rows<T, N>(NH, r0, 2 * G::LPB);
+  const unsigned oa = pair_row_off<T, N>(la - r0, va), ob = pair_row_off<T, N>(lb - r0, vb);
   // Fields of like magnitude share a complex transform: cp = psi_y + i psi_x
   // and cw = omega_x + i omega_y (packing psi with omega, whose sizes differ
   // by ~|k|^2, would bury the stream-function derivatives in the vorticity
   // derivatives' rounding).  Then J = Re(cp * cw).
   T ja[G::R];
   cpx<T> cp[G::R], c[G::R];
-  load_pair_spectrum<T, N>(cp, D + oa, D + 2 * dstride + oa, t, va, va, T(1));
+  load_pair_spectrum_b<T, N>(cp, d0, oa, d2, oa, t, T(1));
   line_fft<N, true>(cp, L, t, tw);
-  load_pair_spectrum<T, N>(c, D + dstride + oa, D + 3 * dstride + oa, t, va, va, T(1));
+  mem_fence_compiler();
+  load_pair_spectrum_b<T, N>(c, d1, oa, d3, oa, t, T(1));
   line_fft<N, true>(c, L, t, tw);
 #pragma unroll
   for (int s = 0; s < G::R; ++s) ja[s] = cp[s].re * c[s].re - cp[s].im * c[s].im;
-  load_pair_spectrum<T, N>(cp, D + ob, D + 2 * dstride + ob, t, vb, vb, T(1));
+  mem_fence_compiler();
+  load_pair_spectrum_b<T, N>(cp, d0, ob, d2, ob, t, T(1));
   line_fft<N, true>(cp, L, t, tw);
-  load_pair_spectrum<T, N>(c, D + dstride + ob, D + 3 * dstride + ob, t, vb, vb, T(1));
+  mem_fence_compiler();
+  load_pair_spectrum_b<T, N>(c, d1, ob, d3, ob, t, T(1));
   line_fft<N, true>(c, L, t, tw);
 #pragma unroll
   for (int s = 0; s < G::R; ++s) c[s] = cpx<T>{ja[s], cp[s].re * c[s].re - cp[s].im * c[s].im};
   line_fft<N, false>(c, L, t, tw);
-  store_pair_halves<T, N>(c, L, t, NH + oa, NH + ob, va, vb);
+  store_pair_halves_b<T, N>(c, L, t, nh, oa, nh, ob);
 }
 
 struct NsColArgs {
@@ -101,19 +109,18 @@ __global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_ns_col(const cpx
   if (MODE == NS_ITER && done[field]) return;  // uniform: a block is one field
   const int col = (tile % tiles_per_field) * WT + c;
   const bool valid = col < ncols;
-  const size_t off = (size_t)field * MY * ncols + col;
   cpx<T>* L = lds + c;
-  auto at = [&](int s) { return off + (size_t)(t + s * G::TL) * ncols; };
+  // columns past the end read zeros and store nothing (buffer range check)
+  auto arr = [&](const cpx<T>* a) { return ColArr<T>(a, field, MY, ncols, col, valid, t, G::TL); };
   cpx<T> w[G::R], v[G::R];
 
   if constexpr (MODE == NS_EXIT) {
 #pragma unroll
-    for (int s = 0; s < G::R; ++s) v[s] = valid ? WN[at(s)] + DK[at(s)] : cpx<T>{0, 0};
+    for (int s = 0; s < G::R; ++s) v[s] = arr(WN).ld(s) + arr(DK).ld(s);
     line_fft<MY, true, WT>(v, L, t, tw);
-    if (valid) {
+    const ColArr<T> out = arr(OUT);
 #pragma unroll
-      for (int s = 0; s < G::R; ++s) OUT[at(s)] = v[s];
-    }
+    for (int s = 0; s < G::R; ++s) out.st(s, v[s]);
     return;
   } else {
     const T kx = (T)(a.kx0 * col);
@@ -122,16 +129,16 @@ __global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_ns_col(const cpx
     double res = 0.0, ens = 0.0;
     // N hybrid -> spectrum (entry: omega's x-transform -> w^n)
 #pragma unroll
-    for (int s = 0; s < G::R; ++s) v[s] = valid ? NH[at(s)] : cpx<T>{0, 0};
+    for (int s = 0; s < G::R; ++s) v[s] = arr(NH).ld(s);
     line_fft<MY, false, WT>(v, L, t, tw);
+    mem_fence_compiler();
+    const ColArr<T> wna = arr(WN), dka = arr(DK), qa = arr(Q);
     if constexpr (MODE == NS_ENTRY) {
 #pragma unroll
       for (int s = 0; s < G::R; ++s) {
         w[s] = v[s];
-        if (valid) {
-          WN[at(s)] = v[s];
-          DK[at(s)] = cpx<T>{0, 0};
-        }
+        wna.st(s, v[s]);
+        dka.st(s, cpx<T>{0, 0});
       }
     } else {
       const T hnu = (T)a.hnu, qdt = (T)a.qdt;
@@ -146,21 +153,19 @@ __global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_ns_col(const cpx
         cpx<T> wn, q, dold;
         if (MODE == NS_FIRST) {
           // w^n = WN + (last step's increment); q = -2 h w^n - dt/2 N(w^n)
-          wn = valid ? WN[at(s)] + DK[at(s)] : cpx<T>{0, 0};
+          wn = wna.ld(s) + dka.ld(s);
           q = cpx<T>{T(-2) * h * wn.re - qdt * nk.re, T(-2) * h * wn.im - qdt * nk.im};
           dold = cpx<T>{0, 0};
-          if (valid) {
-            WN[at(s)] = wn;
-            Q[at(s)] = q;
-          }
+          wna.st(s, wn);
+          qa.st(s, q);
         } else {
-          wn = valid ? WN[at(s)] : cpx<T>{0, 0};
-          q = valid ? Q[at(s)] : cpx<T>{0, 0};
-          dold = valid ? DK[at(s)] : cpx<T>{0, 0};
+          wn = wna.ld(s);
+          q = qa.ld(s);
+          dold = dka.ld(s);
         }
         const T inv = T(1) / (T(1) + h);
         const cpx<T> dnew = cpx<T>{(q.re - qdt * nk.re) * inv, (q.im - qdt * nk.im) * inv};
-        if (valid) DK[at(s)] = dnew;
+        dka.st(s, dnew);
         const double dr = (double)dnew.re - (double)dold.re, di = (double)dnew.im - (double)dold.im;
         res += dr * dr + di * di;
         w[s] = wn + dnew;
@@ -193,10 +198,10 @@ __global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_ns_col(const cpx
         v[s] = mul_i(w[s]) * f;
       }
       line_fft<MY, true, WT>(v, L, t, tw);
-      if (valid) {
+      const ColArr<T> dq = arr(D + q * dstride);
 #pragma unroll
-        for (int s = 0; s < G::R; ++s) D[q * dstride + at(s)] = v[s];
-      }
+      for (int s = 0; s < G::R; ++s) dq.st(s, v[s]);
+      mem_fence_compiler();
     }
   }
 }
@@ -259,11 +264,11 @@ __global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_ns_cq_col(const 
   const int field = tile / tiles_per_field;
   const int col = (tile % tiles_per_field) * WT + c;
   const bool valid = col < ncols;
-  const size_t off = (size_t)field * N * ncols + col;
+  const ColArr<T> xa(XH, field, N, ncols, col, valid, t, G::TL);
   cpx<T>* L = lds + c;
   cpx<T> v[G::R];
 #pragma unroll
-  for (int s = 0; s < G::R; ++s) v[s] = valid ? XH[off + (size_t)(t + s * G::TL) * ncols] : cpx<T>{0, 0};
+  for (int s = 0; s < G::R; ++s) v[s] = xa.ld(s);
   line_fft<N, false, WT>(v, L, t, tw);
   const double kx = kx0 * col;
   double en = 0.0, zz = 0.0;

@@ -26,6 +26,9 @@ namespace pst {
 // FINAL: d = alpha d_old + C2R(W), u_out = u_old + d, prev_out = u_old.
 enum { SG_ENTRY = 0, SG_STEP = 1, SG_FINAL = 2 };
 
+__device__ __forceinline__ float sin_of(float x) { return sin_f32(x); }
+__device__ __forceinline__ double sin_of(double x) { return sin(x); }
+
 template <typename T, int N, int MODE>
 __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_row(
     const cpx<T>* W, FieldRef u_old_f, FieldRef d_old_f, T alpha, FieldRef u_out_f, FieldRef d_out_f,
@@ -39,6 +42,8 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_row(
   const int la = 2 * pair, lb = 2 * pair + 1;
   const bool va = la < nlines, vb = lb < nlines;
   cpx<T>* L = lds + lid * lds_line_stride<T>(N);
+  const int r0 = 2 * blockIdx.x * G::LPB;
+  const unsigned oa = pair_row_off<T, N>(la - r0, va), ob = pair_row_off<T, N>(lb - r0, vb);
   // rows a, b are rows y, y+1 of field f; offsets are relative to each field
   const int f = la >> lny;
   const size_t ra = (size_t)(la & ((1 << lny) - 1)) * N, rb = ra + N;
@@ -60,8 +65,10 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_row(
       u[s] = cpx<T>{ua, ub};
     }
   } else {
-    load_pair_spectrum<T, N>(u, W + (size_t)la * H, W + (size_t)lb * H, t, va, vb, T(1));
+    const FieldBuf wb = pair_rows<T, N>(W, r0, 2 * G::LPB);
+    load_pair_spectrum_b<T, N>(u, wb, oa, wb, ob, t, T(1));
     line_fft<N, true>(u, L, t, tw);
+    mem_fence_compiler();
 #pragma unroll
     for (int s = 0; s < G::R; ++s) {
       const int e = t + s * G::TL;
@@ -81,21 +88,33 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_row(
     }
   }
   if constexpr (MODE != SG_FINAL) {
-    cpx<T> sn[G::R];
+    // S first, from sin(u) in place; u itself is then read back from where
+    // this thread just wrote it (STEP: u_out) or from the input (ENTRY), so
+    // only one line array is live at a time.
 #pragma unroll
-    for (int s = 0; s < G::R; ++s) sn[s] = cpx<T>{sin(u[s].re), sin(u[s].im)};
+    for (int s = 0; s < G::R; ++s) u[s] = cpx<T>{sin_of(u[s].re), sin_of(u[s].im)};
     line_fft<N, false>(u, L, t, tw);
-    store_pair_halves<T, N>(u, L, t, U + (size_t)la * H, U + (size_t)lb * H, va, vb);
-    line_fft<N, false>(sn, L, t, tw);
-    store_pair_halves<T, N>(sn, L, t, S + (size_t)la * H, S + (size_t)lb * H, va, vb);
+    const FieldBuf sb = pair_rows<T, N>(S, r0, 2 * G::LPB);
+    store_pair_halves_b<T, N>(u, L, t, sb, oa, sb, ob);
+    mem_fence_compiler();
+    gptr<const T> src = MODE == SG_ENTRY ? u_old : (gptr<const T>)u_out;
+#pragma unroll
+    for (int s = 0; s < G::R; ++s) {
+      const int e = t + s * G::TL;
+      u[s] = cpx<T>{va ? src[ra + e] : T(0), vb ? src[rb + e] : T(0)};
+    }
+    line_fft<N, false>(u, L, t, tw);
+    const FieldBuf ub = pair_rows<T, N>(U, r0, 2 * G::LPB);
+    store_pair_halves_b<T, N>(u, L, t, ub, oa, ub, ob);
   }
 }
 
 // Column pass over the nx/2+1 half-spectrum columns.
 template <typename T, int N, int WT>
-__global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_sg_col(const cpx<T>* U, const cpx<T>* S, cpx<T>* W, int ncols,
-                                                 int tiles_per_field, const cpx<T>* __restrict__ tw,
-                                                 T kx0, T ky0, T dt2q, T cnum, T c2num, T sc) {
+__global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_sg_col(const cpx<T>* U, const cpx<T>* S, cpx<T>* W,
+                                                                       int ncols, int tiles_per_field,
+                                                                       const cpx<T>* __restrict__ tw, T kx0, T ky0,
+                                                                       T dt2q, T cnum, T c2num, T sc) {
   using G = ColGeom<T, N, WT>;
   extern __shared__ char smem[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
@@ -104,34 +123,38 @@ __global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_sg_col(const cpx
   const int field = tile / tiles_per_field;
   const int col = (tile % tiles_per_field) * WT + c;
   const bool valid = col < ncols;
-  const size_t off = (size_t)field * N * ncols + col;
+  const ColArr<T> Ua(U, field, N, ncols, col, valid, t, G::TL), Sa(S, field, N, ncols, col, valid, t, G::TL),
+      Wa(W, field, N, ncols, col, valid, t, G::TL);
   cpx<T>* L = lds + c;
-  cpx<T> u[G::R], s_[G::R];
-#pragma unroll
-  for (int s = 0; s < G::R; ++s) {
-    const size_t i = off + (size_t)(t + s * G::TL) * ncols;
-    u[s] = valid ? U[i] : cpx<T>{0, 0};
-    s_[s] = valid ? S[i] : cpx<T>{0, 0};
-  }
-  line_fft<N, false, WT>(u, L, t, tw);
-  line_fft<N, false, WT>(s_, L, t, tw);
   const T kx = kx0 * (T)col;
   const T kx2 = kx * kx;
-#pragma unroll
-  for (int s = 0; s < G::R; ++s) {
+  // (c1 - 2) and c2 of mode e of this column: step c1 - 2 = -4a/(1+a)
+  // (cnum 2), start c1 - 1 = -2a/(1+a) (cnum 1)
+  auto coef = [&](int s, T& c1m, T& c2) {
     const int e = t + s * G::TL;
     const T ky = ky0 * (T)(e < N / 2 ? e : e - N);
     const T a = (kx2 + ky * ky) * dt2q;
     const T inv = T(1) / (T(1) + a);
-    // step: c1 - 2 = -4a/(1+a) (cnum 2); start: c1 - 1 = -2a/(1+a) (cnum 1)
-    const T c1m = T(-2) * cnum * a * inv * sc, c2 = c2num * inv * sc;
+    c1m = T(-2) * cnum * a * inv * sc;
+    c2 = c2num * inv * sc;
+  };
+  cpx<T> u[G::R], s_[G::R];
+#pragma unroll
+  for (int s = 0; s < G::R; ++s) u[s] = Ua.ld(s);
+  line_fft<N, false, WT>(u, L, t, tw);
+  mem_fence_compiler();
+#pragma unroll
+  for (int s = 0; s < G::R; ++s) s_[s] = Sa.ld(s);
+  line_fft<N, false, WT>(s_, L, t, tw);
+#pragma unroll
+  for (int s = 0; s < G::R; ++s) {
+    T c1m, c2;
+    coef(s, c1m, c2);
     u[s] = cpx<T>{c1m * u[s].re - c2 * s_[s].re, c1m * u[s].im - c2 * s_[s].im};
   }
   line_fft<N, true, WT>(u, L, t, tw);
-  if (valid) {
 #pragma unroll
-    for (int s = 0; s < G::R; ++s) W[off + (size_t)(t + s * G::TL) * ncols] = u[s];
-  }
+  for (int s = 0; s < G::R; ++s) Wa.st(s, u[s]);
 }
 
 // ----------------------------------------------------------- Hamiltonian ---
@@ -152,17 +175,28 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_h_row(
   const int la = 2 * pair, lb = 2 * pair + 1;
   const bool va = la < nlines, vb = lb < nlines;
   cpx<T>* L = lds + lid * lds_line_stride<T>(N);
-  cpx<T> ub[G::R];
+  const T* ra = f0 + (size_t)la * N;
+  const T* rb = f0 + (size_t)lb * N;
+  const T* qa = f1 + (size_t)la * N;
+  const T* qb = f1 + (size_t)lb * N;
+  // FP64 sums in a rolled loop (one value's sines live at a time)
   double kin = 0.0, pot = 0.0;
-#pragma unroll
+#pragma unroll 1
   for (int s = 0; s < G::R; ++s) {
     const int e = t + s * G::TL;
-    const double a0 = va ? (double)f0[(size_t)la * N + e] : 0.0, a1 = va ? (double)f1[(size_t)la * N + e] : 0.0;
-    const double b0 = vb ? (double)f0[(size_t)lb * N + e] : 0.0, b1 = vb ? (double)f1[(size_t)lb * N + e] : 0.0;
+    const double a0 = va ? (double)ra[e] : 0.0, a1 = va ? (double)qa[e] : 0.0;
+    const double b0 = vb ? (double)rb[e] : 0.0, b1 = vb ? (double)qb[e] : 0.0;
     const double da = (a1 - a0) * inv_dt, db = (b1 - b0) * inv_dt;
     kin += da * da + db * db;
     const double sa0 = sin(0.5 * a0), sa1 = sin(0.5 * a1), sb0 = sin(0.5 * b0), sb1 = sin(0.5 * b1);
     pot += sa0 * sa0 + sa1 * sa1 + sb0 * sb0 + sb1 * sb1;
+  }
+  cpx<T> ub[G::R];
+#pragma unroll
+  for (int s = 0; s < G::R; ++s) {
+    const int e = t + s * G::TL;
+    const double a0 = va ? (double)ra[e] : 0.0, a1 = va ? (double)qa[e] : 0.0;
+    const double b0 = vb ? (double)rb[e] : 0.0, b1 = vb ? (double)qb[e] : 0.0;
     ub[s] = cpx<T>{(T)(0.5 * (a0 + a1)), (T)(0.5 * (b0 + b1))};
   }
   kin = line_sum(red, lid, t, G::TL, kin);
@@ -190,11 +224,11 @@ __global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_sg_h_col(cpx<T>*
   const int field = tile / tiles_per_field;
   const int col = (tile % tiles_per_field) * WT + c;
   const bool valid = col < ncols;
-  const size_t off = (size_t)field * N * ncols + col;
+  const ColArr<T> UBa(UB, field, N, ncols, col, valid, t, G::TL);
   cpx<T>* L = lds + c;
   cpx<T> v[G::R];
 #pragma unroll
-  for (int s = 0; s < G::R; ++s) v[s] = valid ? UB[off + (size_t)(t + s * G::TL) * ncols] : cpx<T>{0, 0};
+  for (int s = 0; s < G::R; ++s) v[s] = UBa.ld(s);
   line_fft<N, false, WT>(v, L, t, tw);
   const double kx = kx0 * col;
   const double w = (col == 0 || col == nx / 2) ? 1.0 : 2.0;

@@ -186,6 +186,29 @@ struct FieldBuf {
   }
 };
 
+// A column tile's view of one complex array laid out [field][N][ncols]:
+// element s of thread (c, t) is row t + s*TL of column col of the block's
+// field (field must be block-uniform).  Columns past the end get an offset
+// beyond the buffer's range, so their loads read zeros and their stores are
+// dropped by the hardware range check.
+template <typename T>
+struct ColArr {
+  FieldBuf b;
+  unsigned o0, ds;
+  __device__ ColArr(const void* array, int field, int N, int ncols, int col, bool valid, int t, int TL)
+      : b((const char*)array + (size_t)field * N * ncols * sizeof(cpx<T>),
+          (unsigned)((size_t)N * ncols * sizeof(cpx<T>))),
+        o0(valid ? (unsigned)(col + t * ncols) * (unsigned)sizeof(cpx<T>) : 0x80000000u),
+        ds((unsigned)(TL * ncols) * (unsigned)sizeof(cpx<T>)) {}
+  __device__ __forceinline__ cpx<T> ld(int s) const { return b.template ldc<T>(o0, s * ds); }
+  __device__ __forceinline__ void st(int s, cpx<T> v) const { b.st(o0, s * ds, v); }
+};
+
+// Keeps the compiler from moving memory accesses across this point (used to
+// stop loads for a later phase being hoisted above a transform, where they
+// would hold registers through it).
+__device__ __forceinline__ void mem_fence_compiler() { asm volatile("" ::: "memory"); }
+
 // Blocks are handed to the 8 XCDs of the chip round robin (block b runs on
 // XCD b mod 8).  Give each XCD a contiguous range of tiles, so that the
 // column tiles sharing a 128-byte line are read through the same L2.
@@ -195,11 +218,43 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
   return x * q + (x < rem ? x : rem) + i;
 }
 
+// Single-precision sine and cosine with the argument reduced in double
+// precision: n = nearest integer to x / (pi/2), r = x - n pi/2 (one double
+// FMA, so |r| <= pi/4 to double accuracy for any |x| below ~1e15), then the
+// Taylor series of sin and cos to degree 9 and 10 in r (truncation below
+// 2e-9 on |r| <= pi/4, under FP32 rounding), and the quadrant n mod 4 picks
+// +-sin r or +-cos r.  Compact (no large-argument branch), which keeps
+// register use low when many values are evaluated at once.
+__device__ __forceinline__ void sincos_f32(float x, float& sn, float& cs) {
+  const double xd = x;
+  const double n = rint(xd * 0.63661977236758134308);       // 2 / pi
+  float r = (float)fma(-n, 1.57079632679489661923, xd);  // pi / 2
+  // |x| beyond ~1e15 (where FP32 carries no phase information) gives a
+  // bounded value; NaN and infinity propagate
+  if (fabsf(r) > 0.8f) r = 0.0f;
+  const double q4 = n - 4.0 * floor(n * 0.25);                 // n mod 4, exact
+  const int q = (int)q4;
+  const float r2 = r * r;
+  // sin r = r (1 - r^2/3! + r^4/5! - r^6/7! + r^8/9!)
+  const float ps = r * (1.0f + r2 * (-1.0f / 6 + r2 * (1.0f / 120 + r2 * (-1.0f / 5040 + r2 * (1.0f / 362880)))));
+  // cos r = 1 - r^2/2! + r^4/4! - r^6/6! + r^8/8! - r^10/10!
+  const float pc =
+      1.0f + r2 * (-0.5f + r2 * (1.0f / 24 + r2 * (-1.0f / 720 + r2 * (1.0f / 40320 + r2 * (-1.0f / 3628800)))));
+  const float s0 = (q & 1) ? pc : ps, c0 = (q & 1) ? ps : pc;
+  sn = (q & 2) ? -s0 : s0;
+  cs = ((q + 1) & 2) ? -c0 : c0;
+}
+__device__ __forceinline__ float sin_f32(float x) {
+  float s, c;
+  sincos_f32(x, s, c);
+  return s;
+}
+
 // v * exp(-i theta), written as v + v*(cos(theta) - 1 - i sin(theta)) with
 // cos(theta) - 1 = -2 sin^2(theta/2): for the small angles of a time step
 // the correction is tiny, so rounding does not bias |v| (a rounded
-// cos(theta) near 1 would).  Short Taylor series for small angles, library
-// sincos otherwise.
+// cos(theta) near 1 would).  Short Taylor series for small angles, the
+// half angle's sine and cosine otherwise.
 __device__ __forceinline__ cpx<float> rotate_neg(cpx<float> v, float th) {
   float cm1, s;
   if (fabsf(th) <= 0.03125f) {
@@ -209,7 +264,7 @@ __device__ __forceinline__ cpx<float> rotate_neg(cpx<float> v, float th) {
     s = th * (1.0f - t2 * (1.0f / 6));
   } else {
     float sh, ch;
-    sincosf(0.5f * th, &sh, &ch);
+    sincos_f32(0.5f * th, sh, ch);
     cm1 = -2.0f * sh * sh;
     s = 2.0f * sh * ch;
   }
@@ -302,6 +357,69 @@ __device__ __forceinline__ void store_pair_halves(const cpx<T> (&v)[line_radix(N
     const cpx<T> sum = zk + zm, dif = zk - zm;
     if (va) A[k] = sum;
     if (vb) B[k] = cpx<T>{dif.im, -dif.re};
+  }
+}
+
+// Row-pair passes reach half-spectrum rows ([rows][N/2+1] complex) through
+// a buffer resource based at the block's first row; a thread passes the
+// byte offset of its row, or kNoRow for a row past the end (loads read
+// zeros, stores are dropped by the hardware range check).
+constexpr unsigned kNoRow = 0x80000000u;
+
+template <typename T, int N>
+__device__ __forceinline__ FieldBuf pair_rows(const void* array, int first_row, int rows) {
+  constexpr size_t rb = (size_t)(N / 2 + 1) * sizeof(cpx<T>);
+  return FieldBuf((const char*)array + (size_t)first_row * rb, (unsigned)(rows * rb));
+}
+template <typename T, int N>
+__device__ __forceinline__ unsigned pair_row_off(int row_in_block, bool valid) {
+  return valid ? (unsigned)(row_in_block * (N / 2 + 1) * (int)sizeof(cpx<T>)) : kNoRow;
+}
+
+// load_pair_spectrum through buffers: A at byte offset oa, B at ob.
+template <typename T, int N>
+__device__ __forceinline__ void load_pair_spectrum_b(cpx<T> (&v)[line_radix(N)], const FieldBuf& A, unsigned oa,
+                                                     const FieldBuf& B, unsigned ob, int t, T scale) {
+  constexpr int TL = N / line_radix(N);
+#pragma unroll
+  for (int s = 0; s < line_radix(N); ++s) {
+    const int e = t + s * TL;
+    const bool lo = e <= N / 2;
+    const unsigned k = (unsigned)(lo ? e : N - e) * (unsigned)sizeof(cpx<T>);
+    cpx<T> a = A.template ldc<T>(oa + k, 0);
+    cpx<T> b = B.template ldc<T>(ob + k, 0);
+    if (e == 0 || e == N / 2) {
+      a.im = 0;
+      b.im = 0;
+    }
+    if (!lo) {
+      a = conj(a);
+      b = conj(b);
+    }
+    v[s] = (a + mul_i(b)) * scale;
+  }
+}
+
+// store_pair_halves through buffers.
+template <typename T, int N>
+__device__ __forceinline__ void store_pair_halves_b(const cpx<T> (&v)[line_radix(N)], cpx<T>* L, int t,
+                                                    const FieldBuf& A, unsigned oa, const FieldBuf& B, unsigned ob) {
+  constexpr int R = line_radix(N);
+  constexpr int TL = N / R;
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < R; ++s) L[lds_idx(t + s * TL)] = v[s];
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s <= R / 2; ++s) {
+    if (s == R / 2 && t != 0) break;
+    const int k = (s < R / 2) ? t + s * TL : N / 2;
+    const cpx<T> zk = L[lds_idx(k)];
+    const cpx<T> zm = conj(L[lds_idx((N - k) & (N - 1))]);
+    const cpx<T> sum = zk + zm, dif = zk - zm;
+    const unsigned kb = (unsigned)k * (unsigned)sizeof(cpx<T>);
+    A.st(oa + kb, 0, sum);
+    B.st(ob + kb, 0, cpx<T>{dif.im, -dif.re});
   }
 }
 

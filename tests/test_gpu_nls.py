@@ -69,6 +69,18 @@ def test_ragged_shapes_and_batches(nx, ny, batch, prec):
         assert rel_err(got[i], ref) < TOL[prec]
 
 
+@pytest.mark.parametrize("prec", [1, 0])
+def test_strong_nonlinear_phase_against_oracle(prec):
+    # per-step nonlinear phase dt g |psi|^2 up to ~0.4, beyond the small-angle
+    # series: the rotation takes the half angle's sine and cosine
+    d = inputs.Domain(12.0, 12.0, -6.0, -6.0)
+    psi0 = inputs.nls_gaussian(64, 64, d, seed=3) * 6.0
+    assert 0.05 * np.max(np.abs(psi0)) ** 2 > 0.3
+    got, _ = run_gpu(psi0, d, 0.05, 1.0, 20, prec)
+    ref, _ = onls.run(psi0, d.lx, d.ly, 0.05, 1.0, 20)
+    assert rel_err(got, ref) < TOL[prec]
+
+
 def test_zero_and_one_step():
     d = inputs.PAPER_DOMAIN
     psi0 = inputs.nls_gaussian(64, 64, d, seed=1)
