@@ -10,6 +10,11 @@
 // is: entry row (FFT_x only), column (half), n-1 x [row, column (full)],
 // row, column (half), exit row (iFFT_x only).  The unnormalised transforms'
 // factors go into the phase coefficient and one scaling in the column pass.
+// H is stored with the rows of each pair (2p, 2p+1) interleaved element by
+// element: H(y, x) sits at (y - y%2) nx + 2x + y%2.  A row pass block owns
+// whole pairs (the first pass reads psi's plain rows, the last writes them
+// back), and a column pass block of W columns then reads and writes
+// 2W-element (64-byte for W = 4, FP32) segments instead of W-element ones.
 // The propagator tables hold E - 1 = (cos - 1, -sin): multiplying as
 // v + v (E - 1) keeps |E| = 1 to within rounding of the small correction;
 // rounded (cos, -sin) pairs carry a bias of |E| near 1 for the energetic
@@ -19,58 +24,78 @@
 
 namespace pst {
 
-// UNI: all lines of a block lie in one field (always so when the field has
-// at least LPB rows); the field is then reached through a buffer resource.
+// Row pass over row pairs: P pairs per block, the two rows of a pair on
+// alternate lanes (l = lane & 1) and interleaved in LDS like a two-column
+// tile.  MODE 0 reads plain rows of psi, MODE 2 writes them; everything else
+// is in the pair-interleaved layout.  UNI: all pairs of a block lie in one
+// field, reached through a buffer resource.
+template <typename T, int N, int VPT, bool SPLIT>
+struct PairGeom {
+  static constexpr int R = VPT;
+  static constexpr int TL = N / VPT;
+  static constexpr int P = TL >= 128 ? 1 : 128 / TL;
+  static constexpr int THREADS = 2 * P * TL;
+  static constexpr int LINE = lds_line_len(N);
+  static constexpr size_t LDS_BYTES = (size_t)P * 2 * LINE * (SPLIT ? sizeof(T) : sizeof(cpx<T>));
+};
+
 template <typename T, int N, int MODE, int VPT, bool SPLIT, bool UNI>
-__global__ __launch_bounds__((RowGeom<T, N, VPT, SPLIT>::THREADS)) void k_nls_row(
-    FieldRef psi, int nlines, int lny, T phase_coef, T scale, const cpx<T>* __restrict__ tw) {
-  using G = RowGeom<T, N, VPT, SPLIT>;
+__global__ __launch_bounds__((PairGeom<T, N, VPT, SPLIT>::THREADS)) void k_nls_row(
+    FieldRef psi, int npairs, int lny, T phase_coef, T scale, const cpx<T>* __restrict__ tw) {
+  using G = PairGeom<T, N, VPT, SPLIT>;
   extern __shared__ char smem[];
-  const int lid = threadIdx.x / G::TL, t = threadIdx.x % G::TL;
-  const int line = blockIdx.x * G::LPB + lid;
-  const bool valid = line < nlines;
-  void* L = SPLIT ? (void*)(reinterpret_cast<T*>(smem) + lid * G::STRIDE)
-                  : (void*)(reinterpret_cast<cpx<T>*>(smem) + lid * G::STRIDE);
-  // lines past the end (a partial last block) recompute the last line and do not store
-  const int lc = valid ? line : nlines - 1;
+  const int l = threadIdx.x & 1, q = threadIdx.x >> 1;
+  const int t = q % G::TL, pl = q / G::TL;
+  const int pair = blockIdx.x * G::P + pl;
+  const bool valid = pair < npairs;
+  // pairs past the end (a partial last block) recompute the last pair and do not store
+  const int pc = valid ? pair : npairs - 1;
   const int ny = 1 << lny;
+  const int r = (2 * pc) & (ny - 1);  // first row of the pair within its field
+  const size_t slot0 = (size_t)pl * 2 * G::LINE + l;
+  void* L = SPLIT ? (void*)(reinterpret_cast<T*>(smem) + slot0) : (void*)(reinterpret_cast<cpx<T>*>(smem) + slot0);
   cpx<T> v[G::R];
   auto body = [&]() {
     if constexpr (MODE == 0) {
-      line_fft<N, false, 1, VPT, SPLIT>(v, L, t, tw);
+      line_fft<N, false, 2, VPT, SPLIT>(v, L, t, tw);
 #pragma unroll
       for (int s = 0; s < G::R; ++s) v[s] = v[s] * scale;
     } else if constexpr (MODE == 1) {
-      line_fft<N, true, 1, VPT, SPLIT>(v, L, t, tw);
+      line_fft<N, true, 2, VPT, SPLIT>(v, L, t, tw);
 #pragma unroll
       for (int s = 0; s < G::R; ++s) v[s] = rotate_neg(v[s], phase_coef * norm2(v[s]));
-      line_fft<N, false, 1, VPT, SPLIT>(v, L, t, tw);
+      line_fft<N, false, 2, VPT, SPLIT>(v, L, t, tw);
     } else {
-      line_fft<N, true, 1, VPT, SPLIT>(v, L, t, tw);
+      line_fft<N, true, 2, VPT, SPLIT>(v, L, t, tw);
 #pragma unroll
       for (int s = 0; s < G::R; ++s) v[s] = v[s] * scale;
     }
   };
+  // element offsets of value s: plain row r + l, or the interleaved pair
+  const unsigned plain0 = (unsigned)((r + l) * N + t), inter0 = (unsigned)(r * N + 2 * t + l);
+  constexpr unsigned plain_ds = G::TL, inter_ds = 2 * G::TL;
+  constexpr bool in_plain = MODE == 0, out_plain = MODE == 2;
+  const unsigned i0 = in_plain ? plain0 : inter0, o0 = out_plain ? plain0 : inter0;
+  const unsigned ids = in_plain ? plain_ds : inter_ds, ods = out_plain ? plain_ds : inter_ds;
+  constexpr unsigned sz = sizeof(cpx<T>);
   if constexpr (UNI) {
-    const int f = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * G::LPB) >> lny);
-    const FieldBuf fb(psi.at(f), (unsigned)((size_t)ny * N * sizeof(cpx<T>)));
-    const unsigned o0 = (unsigned)((lc & (ny - 1)) * N + t) * (unsigned)sizeof(cpx<T>);
-    constexpr unsigned ds = G::TL * sizeof(cpx<T>);
+    const int f = __builtin_amdgcn_readfirstlane((int)(2 * blockIdx.x * G::P) >> lny);
+    const FieldBuf fb(psi.at(f), (unsigned)((size_t)ny * N * sz));
 #pragma unroll
-    for (int s = 0; s < G::R; ++s) v[s] = fb.template ldc<T>(o0, s * ds);
+    for (int s = 0; s < G::R; ++s) v[s] = fb.template ldc<T>(i0 * sz, s * ids * sz);
     body();
     if (valid) {
 #pragma unroll
-      for (int s = 0; s < G::R; ++s) fb.st(o0, s * ds, v[s]);
+      for (int s = 0; s < G::R; ++s) fb.st(o0 * sz, s * ods * sz, v[s]);
     }
   } else {
-    gptr<cpx<T>> g = field<cpx<T>>(psi, lc >> lny) + (size_t)(lc & (ny - 1)) * N;
+    gptr<cpx<T>> g = field<cpx<T>>(psi, (2 * pc) >> lny);
 #pragma unroll
-    for (int s = 0; s < G::R; ++s) v[s] = gload(g + (t + s * G::TL));
+    for (int s = 0; s < G::R; ++s) v[s] = gload(g + (i0 + s * ids));
     body();
     if (valid) {
 #pragma unroll
-      for (int s = 0; s < G::R; ++s) gstore(g + (t + s * G::TL), v[s]);
+      for (int s = 0; s < G::R; ++s) gstore(g + (o0 + s * ods), v[s]);
     }
   }
 }
@@ -88,12 +113,20 @@ __global__ __launch_bounds__((WT * (N / VPT))) __attribute__((amdgpu_waves_per_e
   const bool valid = col < nx;
   const int cc = valid ? col : nx - 1;  // columns past the end recompute the last one, unstored
   const FieldBuf fb(psi.at(fld), (unsigned)((size_t)N * nx * sizeof(cpx<T>)));
-  const unsigned o0 = (unsigned)(cc + t * nx) * (unsigned)sizeof(cpx<T>);
-  const unsigned ds = (unsigned)(G::TL * nx) * (unsigned)sizeof(cpx<T>);  // row step of value s
+  // H(y, cc) of the pair-interleaved layout, y = t + s TL: for even TL the
+  // pair parity of y is that of t (a uniform step per s), for TL = 1 (lines
+  // of 16 or less) it is that of s
+  constexpr bool EVEN = G::TL % 2 == 0;
+  constexpr unsigned sz = sizeof(cpx<T>);
+  const unsigned o0 = (unsigned)((t & ~1) * nx + 2 * cc + (t & 1)) * sz;
+  const unsigned ds = (unsigned)(G::TL * nx) * sz;  // row step of value s
+  // (per-lane, uniform) byte offsets of value s
+  auto voff = [&](int s) { return EVEN ? o0 : (unsigned)((s & ~1) * nx + 2 * cc + (s & 1)) * sz; };
+  auto soff = [&](int s) { return EVEN ? s * ds : 0u; };
   void* L = SPLIT ? (void*)(reinterpret_cast<T*>(smem) + c) : (void*)(reinterpret_cast<cpx<T>*>(smem) + c);
   cpx<T> v[G::R];
 #pragma unroll
-  for (int s = 0; s < G::R; ++s) v[s] = fb.template ldc<T>(o0, s * ds);
+  for (int s = 0; s < G::R; ++s) v[s] = fb.template ldc<T>(voff(s), soff(s));
   line_fft<N, false, WT, VPT, SPLIT>(v, L, t, tw);
   // the propagator loads are issued after the forward transform: hoisted
   // above it they would hold registers through the whole transform
@@ -108,42 +141,43 @@ __global__ __launch_bounds__((WT * (N / VPT))) __attribute__((amdgpu_waves_per_e
   line_fft<N, true, WT, VPT, SPLIT>(v, L, t, tw);
   if (valid) {
 #pragma unroll
-    for (int s = 0; s < G::R; ++s) fb.st(o0, s * ds, v[s]);
+    for (int s = 0; s < G::R; ++s) fb.st(voff(s), soff(s), v[s]);
   }
 }
 
-// Row configuration: 32 values per thread with the split exchange for FP32
-// lines of 8192 (256 threads and 35 KB of LDS per line, so several lines
-// share a CU); 16 values per thread and the complex exchange otherwise.
+// Row configuration: 32 values per thread with the split exchange for lines
+// of 8192 (a pair then takes 512 threads and 70 KB (FP32) or 139 KB (FP64)
+// of LDS); 16 values per thread and the complex exchange otherwise.
 template <typename T, int N>
 struct NlsRowCfg {
-  static constexpr bool BIG = std::is_same<T, float>::value && N >= 8192;
+  static constexpr bool BIG = N >= 8192;
   static constexpr int VPT = BIG ? 32 : line_radix(N);
   static constexpr bool SPLIT = BIG;
 };
 
 template <typename T, int N, int MODE, bool UNI>
-static void launch_row(int nlines, int ny, FieldRef psi, double pc, double scale, const void* tw, hipStream_t s) {
+static void launch_row(int npairs, int ny, FieldRef psi, double pc, double scale, const void* tw, hipStream_t s) {
   using C = NlsRowCfg<T, N>;
-  using G = RowGeom<T, N, C::VPT, C::SPLIT>;
+  using G = PairGeom<T, N, C::VPT, C::SPLIT>;
   auto* k = &k_nls_row<T, N, MODE, C::VPT, C::SPLIT, UNI>;
   allow_lds(k, G::LDS_BYTES);
-  hipLaunchKernelGGL(k, dim3((nlines + G::LPB - 1) / G::LPB), dim3(G::THREADS), G::LDS_BYTES, s, psi, nlines,
+  hipLaunchKernelGGL(k, dim3((npairs + G::P - 1) / G::P), dim3(G::THREADS), G::LDS_BYTES, s, psi, npairs,
                      ilog2c(ny), (T)pc, (T)scale, (const cpx<T>*)tw);
 }
 
 template <typename T>
 static hipError_t row(int nx, int nlines, int ny, FieldRef psi, int mode, double pc, double scale,
                       const void* tw, hipStream_t s) {
+  if (ny % 2 != 0 || nlines % 2 != 0) return hipErrorInvalidValue;
   bool ok = dispatch_n(nx, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
     using C = NlsRowCfg<T, N>;
-    constexpr int LPB = RowGeom<T, N, C::VPT, C::SPLIT>::LPB;
-    const bool uni = LPB == 1 || ny >= LPB;
+    constexpr int P = PairGeom<T, N, C::VPT, C::SPLIT>::P;
+    const bool uni = 2 * P <= ny;
     auto go = [&](auto m) {
       constexpr int MODE = decltype(m)::value;
-      if (uni) launch_row<T, N, MODE, true>(nlines, ny, psi, pc, scale, tw, s);
-      else launch_row<T, N, MODE, false>(nlines, ny, psi, pc, scale, tw, s);
+      if (uni) launch_row<T, N, MODE, true>(nlines / 2, ny, psi, pc, scale, tw, s);
+      else launch_row<T, N, MODE, false>(nlines / 2, ny, psi, pc, scale, tw, s);
     };
     if (mode == 0) go(IntC<0>{});
     else if (mode == 1) go(IntC<1>{});
