@@ -158,6 +158,115 @@ def bench_ns(b, inputs):
     return {"pt_steps_per_s": pts / el, "steps": steps, "ms_per_step": el / steps * 1e3}
 
 
+def time_nls(b, inputs, n, prec, batch, steps, dt=1e-3, variant=None, plans=1):
+    """grid-pt-steps/s of NLS split steps: `plans` separate one-field plans
+    stepped one after another (plain path) when plans > 1, else one plan of
+    `batch` fields."""
+    import torch
+    d = inputs.PAPER_DOMAIN
+    cdt = torch.complex64 if prec == b.PST_FP32 else torch.complex128
+    psi0 = torch.from_numpy(inputs.nls_gaussian(n, n, d, seed=0)).to("cuda", cdt)
+    if plans > 1:
+        ps = [b.Plan(n, n, b.PST_C2C, prec, 1) for _ in range(plans)]
+        fs = [psi0.reshape(1, n, n).clone() for _ in range(plans)]
+        for p in ps:
+            p.autotune("nls")
+        run = lambda k: [p.nls_step(f, d, dt, 1.0, k) for p, f in zip(ps, fs)]
+        pts = plans * n * n
+    else:
+        p = b.Plan(n, n, b.PST_C2C, prec, batch)
+        if variant is None:
+            p.autotune("nls")
+        else:
+            p.set_column_variant(variant)
+        f = psi0.reshape(1, n, n).repeat(batch, 1, 1).contiguous()
+        run = lambda k: p.nls_step(f, d, dt, 1.0, k)
+        pts = batch * n * n
+    run(5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(steps)
+    torch.cuda.synchronize()
+    return pts * steps / (time.perf_counter() - t0)
+
+
+def bench_nls_cases(b, inputs):
+    """Cases beside the headline: FP64 4096^2 and a batch of 4 x 4096^2
+    FP32 (fields that cannot stay in the 256 MB last-level cache), batched vs
+    plain stepping of 4 x 1024^2, and the headline with each column variant
+    (the autotuner's candidates)."""
+    out = {
+        "nls_4096_fp64": time_nls(b, inputs, 4096, b.PST_FP64, 1, 100),
+        "nls_4096x4_fp32": time_nls(b, inputs, 4096, b.PST_FP32, 4, 100),
+        "nls_1024x4_fp32_batched": time_nls(b, inputs, 1024, b.PST_FP32, 4, 400),
+        "nls_1024x4_fp32_plain": time_nls(b, inputs, 1024, b.PST_FP32, 1, 400, plans=4),
+    }
+    nv = len(b.column_variants(b.PST_FP32, 4096, True))
+    out["nls_4096_fp32_by_column_variant"] = [time_nls(b, inputs, 4096, b.PST_FP32, 1, 200, variant=v)
+                                              for v in range(nv)]
+    out["unit"] = "grid-pt-steps/s"
+    return out
+
+
+def bench_sweep(b, inputs):
+    """The paper's grid sweeps (its Tables 2-4 workloads), FP64 as in the
+    paper and FP32: NLS 20 steps of 1e-5 on [-5pi,5pi)^2 (64^2-8192^2),
+    sine-Gordon 500 steps of 1e-3 (64^2-4096^2), Navier-Stokes Taylor-Green
+    20 steps of 1.25e-3 on [0,1)^2, nu 0.1, tol 1e-10 (64^2-4096^2).  Seconds
+    for the paper's step count, loop only, one field, default tiles after
+    autotuning."""
+    import numpy as np
+    import torch
+    d = inputs.PAPER_DOMAIN
+    res = {"nls": {}, "sg": {}, "ns": {}}
+    for prec, name in ((b.PST_FP64, "fp64"), (b.PST_FP32, "fp32")):
+        cdt = torch.complex128 if prec == b.PST_FP64 else torch.complex64
+        rdt = torch.float64 if prec == b.PST_FP64 else torch.float32
+        for e in range(6, 14):
+            n = 1 << e
+            p = b.Plan(n, n, b.PST_C2C, prec, 1)
+            p.autotune("nls")
+            f = torch.from_numpy(inputs.nls_gaussian(n, n, d, seed=0)).to("cuda", cdt).reshape(1, n, n)
+            p.nls_step(f, d, 1e-5, 1.0, 20)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p.nls_step(f, d, 1e-5, 1.0, 20)
+            torch.cuda.synchronize()
+            res["nls"][f"{name}_{n}"] = time.perf_counter() - t0
+            del p, f
+        for e in range(6, 13):
+            n = 1 << e
+            p = b.Plan(n, n, b.PST_R2C, prec, 1)
+            p.autotune("sg")
+            u0 = torch.from_numpy(inputs.sg_gaussian(n, n, d, seed=0)[0]).to("cuda", rdt).reshape(1, n, n)
+            up, uc = torch.empty_like(u0), torch.empty_like(u0)
+            p.sg_start(u0, torch.zeros_like(u0), up, uc, d, 1e-3)
+            p.sg_step(up, uc, d, 1e-3, 5)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p.sg_step(up, uc, d, 1e-3, 500)
+            torch.cuda.synchronize()
+            res["sg"][f"{name}_{n}"] = time.perf_counter() - t0
+            del p, u0, up, uc
+            p = b.Plan(n, n, b.PST_R2C, prec, 1)
+            p.autotune("ns")
+            w0 = torch.from_numpy(inputs.taylor_green(n, 0.0, 0.1)).to("cuda", rdt).reshape(1, n, n)
+            w = w0.clone()
+            p.ns_step(w, inputs.NS_DOMAIN, 1.25e-3, 0.1, 2, tol=1e-10)
+            w.copy_(w0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p.ns_step(w, inputs.NS_DOMAIN, 1.25e-3, 0.1, 20, tol=1e-10)
+            torch.cuda.synchronize()
+            res["ns"][f"{name}_{n}"] = time.perf_counter() - t0
+            exact = inputs.taylor_green(n, 20 * 1.25e-3, 0.1)
+            res["ns"][f"{name}_{n}_max_err"] = float(np.max(np.abs(w[0].double().cpu().numpy() - exact)))
+            del p, w, w0
+        torch.cuda.empty_cache()
+    res["unit"] = "s for the paper's step count"
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,7 +276,9 @@ def main():
     ap.add_argument("--prec", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", type=int, default=512, help="requests in the serving mix (0 = skip)")
-    ap.add_argument("--extra", action="store_true", help="also time sine-Gordon and Navier-Stokes batches")
+    ap.add_argument("--extra", action="store_true",
+                    help="also time sine-Gordon and Navier-Stokes batches and more NLS cases")
+    ap.add_argument("--sweep", action="store_true", help="also run the paper's grid sweeps (Tables 2-4)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -257,6 +368,9 @@ def main():
     if args.extra:
         out["sine_gordon_2048x16"] = bench_sg(b, inputs)
         out["navier_stokes_uneven"] = bench_ns(b, inputs)
+        out["nls_cases"] = bench_nls_cases(b, inputs)
+    if args.sweep:
+        out["paper_sweep"] = bench_sweep(b, inputs)
     if args.serve > 0:
         out["serving"] = bench_serve(args.serve)
     if not args.no_cpu_baseline:

@@ -145,6 +145,48 @@ __global__ __launch_bounds__((WT * (N / VPT))) __attribute__((amdgpu_waves_per_e
   }
 }
 
+// Long lines (N/VPT >= 256 threads), in-place pass (MODE 1): one line per
+// block over the pair layout; line y reads every other element of its
+// pair's span.  Blocks are
+// mapped to lines so that each XCD takes a contiguous range of lines: the
+// two lines of a pair run side by side on one XCD and share its L2.
+template <typename T, int N, int MODE, int VPT, bool SPLIT>
+__global__ __launch_bounds__((N / VPT)) void k_nls_row1(FieldRef psi, int lny, T phase_coef, T scale,
+                                                         const cpx<T>* __restrict__ tw) {
+  constexpr int TL = N / VPT;
+  extern __shared__ char smem[];
+  const int t = threadIdx.x;
+  const int line = xcd_tile(blockIdx.x, gridDim.x);
+  const int ny = 1 << lny;
+  const int y = line & (ny - 1), l = y & 1, r = y - l;
+  void* L = smem;
+  cpx<T> v[VPT];
+  const unsigned plain0 = (unsigned)(y * N + t), inter0 = (unsigned)(r * N + 2 * t + l);
+  constexpr bool in_plain = MODE == 0, out_plain = MODE == 2;
+  const unsigned i0 = in_plain ? plain0 : inter0, o0 = out_plain ? plain0 : inter0;
+  constexpr unsigned ids = in_plain ? TL : 2 * TL, ods = out_plain ? TL : 2 * TL;
+  constexpr unsigned sz = sizeof(cpx<T>);
+  const FieldBuf fb(psi.at(line >> lny), (unsigned)((size_t)ny * N * sz));
+#pragma unroll
+  for (int s = 0; s < VPT; ++s) v[s] = fb.template ldc<T>(i0 * sz, s * ids * sz);
+  if constexpr (MODE == 0) {
+    line_fft<N, false, 1, VPT, SPLIT>(v, L, t, tw);
+#pragma unroll
+    for (int s = 0; s < VPT; ++s) v[s] = v[s] * scale;
+  } else if constexpr (MODE == 1) {
+    line_fft<N, true, 1, VPT, SPLIT>(v, L, t, tw);
+#pragma unroll
+    for (int s = 0; s < VPT; ++s) v[s] = rotate_neg(v[s], phase_coef * norm2(v[s]));
+    line_fft<N, false, 1, VPT, SPLIT>(v, L, t, tw);
+  } else {
+    line_fft<N, true, 1, VPT, SPLIT>(v, L, t, tw);
+#pragma unroll
+    for (int s = 0; s < VPT; ++s) v[s] = v[s] * scale;
+  }
+#pragma unroll
+  for (int s = 0; s < VPT; ++s) fb.st(o0 * sz, s * ods * sz, v[s]);
+}
+
 // Row configuration: 32 values per thread with the split exchange for lines
 // of 8192 (a pair then takes 512 threads and 70 KB (FP32) or 139 KB (FP64)
 // of LDS); 16 values per thread and the complex exchange otherwise.
@@ -176,8 +218,19 @@ static hipError_t row(int nx, int nlines, int ny, FieldRef psi, int mode, double
     const bool uni = 2 * P <= ny;
     auto go = [&](auto m) {
       constexpr int MODE = decltype(m)::value;
-      if (uni) launch_row<T, N, MODE, true>(nlines / 2, ny, psi, pc, scale, tw, s);
-      else launch_row<T, N, MODE, false>(nlines / 2, ny, psi, pc, scale, tw, s);
+      // (only the in-place interleaved pass: the entry and exit passes convert
+      // between layouts, and a pair's two rows must then be owned by one block)
+      if constexpr (MODE == 1 && N / C::VPT >= 256) {
+        auto* k = &k_nls_row1<T, N, MODE, C::VPT, C::SPLIT>;
+        constexpr size_t lds = (size_t)lds_line_len(N) * (C::SPLIT ? sizeof(T) : sizeof(cpx<T>));
+        allow_lds(k, lds);
+        hipLaunchKernelGGL(k, dim3(nlines), dim3(N / C::VPT), lds, s, psi, ilog2c(ny), (T)pc, (T)scale,
+                           (const cpx<T>*)tw);
+      } else if (uni) {
+        launch_row<T, N, MODE, true>(nlines / 2, ny, psi, pc, scale, tw, s);
+      } else {
+        launch_row<T, N, MODE, false>(nlines / 2, ny, psi, pc, scale, tw, s);
+      }
     };
     if (mode == 0) go(IntC<0>{});
     else if (mode == 1) go(IntC<1>{});
