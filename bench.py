@@ -39,9 +39,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel: str, n_pts: int):
+def traffic_from_profile(kernel: str, column_variant: int):
     """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel sources."""
+    taken on the current kernel sources and (for the column pass) the same
+    column variant."""
     path = os.path.join(ROOT, "profiles", "nls_4096_fp32_traffic.json")
     if not os.path.exists(path):
         return None
@@ -49,7 +50,9 @@ def traffic_from_profile(kernel: str, n_pts: int):
     if rec.get("source_hash") != kernel_source_hash():
         return None
     k = rec.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("bytes_per_launch")
+    if k is None or k.get("column_variant", column_variant) != column_variant:
+        return None
+    return k.get("bytes_per_launch")
 
 
 def cpu_baseline(n: int, dt: float, budget_s: float = 15.0):
@@ -327,18 +330,20 @@ def main():
     alg_bytes = BYTES_PER_PT_PASS[prec] * n * n
     achieved = alg_bytes / avg_s / 1e9
     kname = {"nls_row": "k_nls_row", "nls_col": "k_nls_col"}[dom]
-    traffic = traffic_from_profile(kname, n * n)
+    traffic = traffic_from_profile(kname, col_variant) if (n, prec) == (4096, b.PST_FP32) else None
 
-    # device-to-device copy bandwidth of the same field size, for context
-    src = torch.empty(2 * alg_bytes // 2, dtype=torch.uint8, device="cuda")
+    # device-to-device copy bandwidth, for context (1 GiB each way: far larger
+    # than the caches, also the calibration kernel for the HBM byte counters)
+    src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for _ in range(20):
+    for _ in range(5):
         dst.copy_(src)
     torch.cuda.synchronize()
-    copy_gbs = 2 * src.numel() * 20 / (time.perf_counter() - t1) / 1e9
+    copy_gbs = 2 * src.numel() * 5 / (time.perf_counter() - t1) / 1e9
+    del src, dst
 
     out = {
         "metric": "grid-pt-steps/s & %HBM roofline, 2D NLS 4096^2",
