@@ -141,14 +141,18 @@ def bench_sg(b, inputs):
 
 def bench_ns(b, inputs):
     """Navier-Stokes uneven batch: 4 x 1024^2 + 4 x 2048^2 FP32 random-phase
-    vorticity, nu 1e-3, dt 1e-3, adaptive fixed point (tol 1e-10), through
-    solve_batch."""
+    vorticity, nu 1e-3, adaptive fixed point (tol 1e-10), through
+    solve_batch.  dt 2.5e-4: at 1e-3 the scheme's fixed-point iteration
+    diverges for these grids (it does in the FP64 oracle too), at 2.5e-4 it
+    contracts in about 5 iterations per step.  The run is checked to stay
+    finite and converged."""
     import torch
-    steps = 100
+    steps, dt = 100, 2.5e-4
     fields = [torch.from_numpy(inputs.ns_random_phase(1024 if s < 4 else 2048, seed=s)).to("cuda", torch.float32)
               for s in range(8)]
-    pr = b.make_params("ns", inputs.NS_DOMAIN, 1e-3, nu=1e-3, tol=1e-10, max_iter=50)
-    reqs = [{"eq": "ns", "f0": f, "params": pr, "nsteps": 5} for f in fields]
+    pr = b.make_params("ns", inputs.NS_DOMAIN, dt, nu=1e-3, tol=1e-10, max_iter=50)
+    st = [torch.full((1,), -1, dtype=torch.int32, device="cuda") for _ in fields]
+    reqs = [{"eq": "ns", "f0": f, "params": pr, "nsteps": 5, "dev_status": s} for f, s in zip(fields, st)]
     b.solve_batch(reqs)
     torch.cuda.synchronize()
     for r in reqs:
@@ -157,8 +161,10 @@ def bench_ns(b, inputs):
     b.solve_batch(reqs)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    ok = all(int(s.item()) == b.PST_OK for s in st) and all(bool(torch.isfinite(f).all()) for f in fields)
     pts = 4 * (1024 ** 2 + 2048 ** 2) * steps
-    return {"pt_steps_per_s": pts / el, "steps": steps, "ms_per_step": el / steps * 1e3}
+    return {"pt_steps_per_s": pts / el, "steps": steps, "dt": dt, "ms_per_step": el / steps * 1e3,
+            "all_converged_and_finite": ok}
 
 
 def time_nls(b, inputs, n, prec, batch, steps, dt=1e-3, variant=None, plans=1):

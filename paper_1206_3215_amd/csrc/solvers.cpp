@@ -7,6 +7,8 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
+#include <thread>
 #include <tuple>
 #include <utility>
 #include <vector>
@@ -484,8 +486,14 @@ struct BatchPlan {
   Plan* pl = nullptr;
   void** dtab = nullptr;  // device: cap x {f0, f1, status slot}
   int* dfst = nullptr;    // device: per-field status (NS)
+  // chunk schedules (fields, steps) seen once, and the graphs of those seen
+  // again: a schedule is captured on its second occurrence and replayed
+  // from the third on, so one-off schedules (a serving loop's changing mix)
+  // never pay for a capture
+  std::map<std::vector<uintptr_t>, int> seen;
   std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
 };
+constexpr size_t kMaxGraphs = 64, kMaxSeen = 4096;
 
 std::mutex g_batch_mu;
 std::map<GroupKey, BatchPlan> g_batch_plans;
@@ -548,7 +556,12 @@ static pst_status run_chunk(BatchPlan& bp, int eq, const void* params, int nf, i
                             const std::vector<uintptr_t>& key) {
   Plan* pl = bp.pl;
   const int cap = pl->batch;
-  pl->batch = nf;
+  pl->batch = nf;  // the chunk's field count; restored on every return
+  struct Restore {
+    Plan* pl;
+    int cap;
+    ~Restore() { pl->batch = cap; }
+  } restore{pl, cap};
   FieldRef f0, f1;
   f0.table = bp.dtab;
   f1.table = bp.dtab + cap;
@@ -561,10 +574,21 @@ static pst_status run_chunk(BatchPlan& bp, int eq, const void* params, int nf, i
     if (eq == PST_SG) return sg_run(pl, f0, f1, static_cast<const pst_sg_params*>(params), k);
     return ns_run(pl, f0, static_cast<const pst_ns_params*>(params), k, nullptr, fst);
   };
+  auto g = bp.graphs.end();
+  if (capture) {
+    g = bp.graphs.find(key);
+    if (g == bp.graphs.end()) {
+      if (bp.seen.size() >= kMaxSeen) bp.seen.clear();
+      capture = bp.seen[key]++ > 0;
+    }
+  }
+  if (capture && g == bp.graphs.end() && bp.graphs.size() >= kMaxGraphs) {
+    for (auto& e : bp.graphs) hipGraphExecDestroy(e.second);
+    bp.graphs.clear();
+  }
   if (!capture) {
     st = launch();
   } else {
-    auto g = bp.graphs.find(key);
     if (g == bp.graphs.end()) {
       hipGraph_t graph;
       st = hip_check(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal), "begin capture");
@@ -582,7 +606,6 @@ static pst_status run_chunk(BatchPlan& bp, int eq, const void* params, int nf, i
     }
     if (st == PST_OK) st = hip_check(hipGraphLaunch(g->second, pl->stream), "graph launch");
   }
-  pl->batch = cap;
   return st;
 }
 
@@ -616,30 +639,42 @@ extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stre
   hipEvent_t fork;
   TRY(hip_check(hipEventCreateWithFlags(&fork, hipEventDisableTiming), "hipEventCreate"));
   TRY(hip_check(hipEventRecord(fork, caller), "hipEventRecord"));
-  std::vector<hipEvent_t> joins;
+  // Prepare every group on this thread (plan cache, autotuning, checks).
+  struct Job {
+    size_t gi;
+    BatchPlan* bp;
+    bool adaptive;  // NS with a convergence test: host checks once per step
+  };
+  std::vector<Job> jobs;
   pst_status result = PST_OK;
   for (size_t gi = 0; gi < groups.size() && result == PST_OK; ++gi) {
-    const std::vector<int>& g = groups[gi];
-    const pst_request& r0 = reqs[g[0]];
+    const pst_request& r0 = reqs[groups[gi][0]];
     hipStream_t s = g_side_streams[gi];
     result = hip_check(hipStreamWaitEvent(s, fork, 0), "hipStreamWaitEvent");
     if (result != PST_OK) break;
-    // validate the shared parameters through the single-plan checks
     int cap = 1;
-    while (cap < (int)g.size()) cap <<= 1;
+    while (cap < (int)groups[gi].size()) cap <<= 1;
     BatchPlan* bp = nullptr;
     if ((result = batch_plan(r0, cap, s, &bp)) != PST_OK) break;
+    // validate the shared parameters through the single-plan checks
     Plan* pl = bp->pl;
-    cap = pl->batch;
     if (r0.eq == PST_NLS) result = nls_check(pl, static_cast<const pst_nls_params*>(r0.params), 0);
     else if (r0.eq == PST_SG) result = sg_check(pl, static_cast<const pst_sg_params*>(r0.params), "solve_batch");
     else result = ns_check(pl, static_cast<const pst_ns_params*>(r0.params), 0);
-    if (result != PST_OK) break;
-    const bool fixed = r0.eq != PST_NS || static_cast<const pst_ns_params*>(r0.params)->fixed_iters > 0;
+    const bool adaptive = r0.eq == PST_NS && static_cast<const pst_ns_params*>(r0.params)->fixed_iters <= 0;
+    jobs.push_back({gi, bp, adaptive});
+  }
+  std::vector<hipEvent_t> joins(jobs.size(), nullptr);
+  auto run_group = [&](size_t ji) -> pst_status {
+    const std::vector<int>& g = groups[jobs[ji].gi];
+    BatchPlan* bp = jobs[ji].bp;
+    const pst_request& r0 = reqs[g[0]];
+    hipStream_t s = g_side_streams[jobs[ji].gi];
+    const int cap = bp->pl->batch;
     std::vector<int> left(g.size());
     for (size_t j = 0; j < g.size(); ++j) left[j] = reqs[g[j]].nsteps;
-    if (r0.eq == PST_NS) result = hip_check(hipMemsetAsync(bp->dfst, 0, cap * sizeof(int), s), "clear status");
-    while (result == PST_OK) {
+    if (r0.eq == PST_NS) TRY(hip_check(hipMemsetAsync(bp->dfst, 0, cap * sizeof(int), s), "clear status"));
+    while (true) {
       std::vector<int> act;
       int k = 0;
       for (size_t j = 0; j < g.size(); ++j)
@@ -660,13 +695,11 @@ extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stre
       }
       key.push_back((uintptr_t)k);
       key.push_back((uintptr_t)act.size());
-      result = hip_check(hipMemcpyAsync(bp->dtab, tab.data(), tab.size() * sizeof(void*), hipMemcpyHostToDevice, s),
-                         "upload field table");
-      if (result != PST_OK) break;
-      result = run_chunk(*bp, r0.eq, r0.params, (int)act.size(), k, fixed, key);
+      TRY(hip_check(hipMemcpyAsync(bp->dtab, tab.data(), tab.size() * sizeof(void*), hipMemcpyHostToDevice, s),
+                    "upload field table"));
+      TRY(run_chunk(*bp, r0.eq, r0.params, (int)act.size(), k, !jobs[ji].adaptive, key));
       for (int a : act) left[a] -= k;
     }
-    if (result != PST_OK) break;
     // per-request device status
     std::vector<int*> stp(g.size());
     bool any = false;
@@ -675,25 +708,49 @@ extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stre
       any = any || stp[j] != nullptr;
     }
     if (any) {
-      if (r0.eq != PST_NS) result = hip_check(hipMemsetAsync(bp->dfst, 0, cap * sizeof(int), s), "clear status");
+      if (r0.eq != PST_NS) TRY(hip_check(hipMemsetAsync(bp->dfst, 0, cap * sizeof(int), s), "clear status"));
       int** dst = reinterpret_cast<int**>(bp->dtab + 3 * cap);
-      if (result == PST_OK)
-        result = hip_check(hipMemcpyAsync(dst, stp.data(), g.size() * sizeof(int*), hipMemcpyHostToDevice, s),
-                           "upload status table");
-      if (result == PST_OK) {
-        hipLaunchKernelGGL(k_scatter_status, dim3(((int)g.size() + 255) / 256), dim3(256), 0, s, bp->dfst, dst,
-                           (int)g.size());
-        result = hip_check(hipGetLastError(), "status scatter");
-      }
+      TRY(hip_check(hipMemcpyAsync(dst, stp.data(), g.size() * sizeof(int*), hipMemcpyHostToDevice, s),
+                    "upload status table"));
+      hipLaunchKernelGGL(k_scatter_status, dim3(((int)g.size() + 255) / 256), dim3(256), 0, s, bp->dfst, dst,
+                         (int)g.size());
+      TRY(hip_check(hipGetLastError(), "status scatter"));
     }
     hipEvent_t j;
-    if (result == PST_OK) result = hip_check(hipEventCreateWithFlags(&j, hipEventDisableTiming), "hipEventCreate");
-    if (result == PST_OK) {
-      hipEventRecord(j, s);
-      joins.push_back(j);
-    }
+    TRY(hip_check(hipEventCreateWithFlags(&j, hipEventDisableTiming), "hipEventCreate"));
+    TRY(hip_check(hipEventRecord(j, s), "hipEventRecord"));
+    joins[ji] = j;
+    return PST_OK;
+  };
+  // Fixed-schedule groups first: their launches (graph replays) are
+  // asynchronous.  Adaptive NS groups wait on the host once per step, so
+  // each runs on a host thread of its own and their waits overlap with each
+  // other and with the device work already queued.
+  std::vector<size_t> adaptive;
+  for (size_t ji = 0; ji < jobs.size() && result == PST_OK; ++ji) {
+    if (jobs[ji].adaptive) adaptive.push_back(ji);
+    else result = run_group(ji);
+  }
+  if (result == PST_OK && adaptive.size() == 1) {
+    result = run_group(adaptive[0]);
+  } else if (result == PST_OK && !adaptive.empty()) {
+    std::vector<pst_status> st(adaptive.size(), PST_OK);
+    std::vector<std::string> msg(adaptive.size());
+    std::vector<std::thread> th;
+    int dev = 0;
+    hipGetDevice(&dev);
+    for (size_t a = 0; a < adaptive.size(); ++a)
+      th.emplace_back([&, a]() {
+        hipSetDevice(dev);
+        st[a] = run_group(adaptive[a]);
+        if (st[a] != PST_OK) msg[a] = pst_last_error();
+      });
+    for (auto& t : th) t.join();
+    for (size_t a = 0; a < adaptive.size() && result == PST_OK; ++a)
+      if (st[a] != PST_OK) result = fail(st[a], "%s", msg[a].c_str());
   }
   for (hipEvent_t j : joins) {
+    if (j == nullptr) continue;
     hipStreamWaitEvent(caller, j, 0);
     hipEventDestroy(j);
   }

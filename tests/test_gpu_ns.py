@@ -115,6 +115,20 @@ def test_full_size_random_phase_short(n):
     assert rel_err(got[0], ref) < TOL[0]
 
 
+@pytest.mark.parametrize("n", [1024, 2048])
+def test_full_size_random_phase_adaptive_converges(n):
+    # the benchmark configuration (FP32, tol 1e-10, dt 2.5e-4): every step
+    # converges in a few iterations and the field stays finite; the first
+    # step agrees with the FP64 oracle's adaptive step
+    w0 = inputs.ns_random_phase(n, seed=5)
+    got, its, st, _ = gpu_ns(w0, D1, 2.5e-4, 1e-3, 3, 0, tol=1e-10, max_iter=50, want_iters=True)
+    assert st == 0
+    assert np.all(np.isfinite(got)) and np.all((its >= 2) & (its <= 12))
+    one, _, _, _ = gpu_ns(w0, D1, 2.5e-4, 1e-3, 1, 0, tol=1e-10, max_iter=50)
+    ref, _, ok = ons.run(w0, 1.0, 1.0, 2.5e-4, 1e-3, 1, tol=1e-10, max_iter=50)
+    assert ok and rel_err(one[0], ref) < TOL[0]
+
+
 def test_batch_member_bitwise_equal_alone():
     w0 = np.stack([inputs.ns_random_phase(128, seed=s) for s in range(4)])
     got, _, _, _ = gpu_ns(w0, D1, 1e-3, 1e-3, 5, 0, tol=1e-10)

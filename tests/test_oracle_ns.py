@@ -153,3 +153,24 @@ def test_two_thirds_rule_removes_aliasing():
     w = fields(n)["w"]
     got = ns.jacobian_hat(sp.rfft2(w), w.shape, 1.0, 1.0)
     assert np.max(np.abs(got - expect)) < 1e-9 * np.max(np.abs(expect))
+
+
+def test_fixed_point_diverges_at_stated_dt_and_contracts_at_quarter_dt():
+    # Random-phase vorticity (unit energy, spectrum k^4 exp(-(k/8)^2)), nu 1e-3
+    # on a 512^2 grid: with dt 1e-3 the fixed-point map's gain on the modes
+    # near k* = sqrt(2/(dt nu)) is about dt |u| k*/2 ~ 1, the iteration stops
+    # converging within two steps and the field blows up; with dt 2.5e-4 it
+    # converges every step in a handful of iterations.
+    w0 = inputs.ns_random_phase(512, seed=1)
+    w, conv_flags = w0, []
+    with np.errstate(all="ignore"):
+        for _ in range(6):
+            w, it, conv = ns.step(w, 1.0, 1.0, 1e-3, 1e-3, tol=1e-10, max_iter=30)
+            conv_flags.append(conv)
+    assert not all(conv_flags)
+    assert not np.all(np.isfinite(w)) or np.max(np.abs(w)) > 10 * np.max(np.abs(w0))
+    w = w0
+    for _ in range(3):
+        w, it, conv = ns.step(w, 1.0, 1.0, 2.5e-4, 1e-3, tol=1e-10, max_iter=30)
+        assert conv and it <= 8
+    assert np.all(np.isfinite(w))
