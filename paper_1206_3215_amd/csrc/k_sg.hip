@@ -43,7 +43,9 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_row(
   const bool va = la < nlines, vb = lb < nlines;
   cpx<T>* L = lds + lid * lds_line_stride<T>(N);
   const int r0 = 2 * blockIdx.x * G::LPB;
-  const unsigned oa = pair_row_off<T, N>(la - r0, va), ob = pair_row_off<T, N>(lb - r0, vb);
+  // U, S, W hold the rows of each pair interleaved (see ColArr)
+  const unsigned oa = pair_row_off_il<T, N>(la - r0, va), ob = pair_row_off_il<T, N>(lb - r0, vb);
+  constexpr unsigned kst = 2 * sizeof(cpx<T>);
   // rows a, b are rows y, y+1 of field f; offsets are relative to each field
   const int f = la >> lny;
   const size_t ra = (size_t)(la & ((1 << lny) - 1)) * N, rb = ra + N;
@@ -66,7 +68,7 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_row(
     }
   } else {
     const FieldBuf wb = pair_rows<T, N>(W, r0, 2 * G::LPB);
-    load_pair_spectrum_b<T, N>(u, wb, oa, wb, ob, t, T(1));
+    load_pair_spectrum_b<T, N>(u, wb, oa, wb, ob, t, T(1), kst);
     line_fft<N, true>(u, L, t, tw);
     mem_fence_compiler();
 #pragma unroll
@@ -95,7 +97,7 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_row(
     for (int s = 0; s < G::R; ++s) u[s] = cpx<T>{sin_of(u[s].re), sin_of(u[s].im)};
     line_fft<N, false>(u, L, t, tw);
     const FieldBuf sb = pair_rows<T, N>(S, r0, 2 * G::LPB);
-    store_pair_halves_b<T, N>(u, L, t, sb, oa, sb, ob);
+    store_pair_halves_b<T, N>(u, L, t, sb, oa, sb, ob, kst);
     mem_fence_compiler();
     gptr<const T> src = MODE == SG_ENTRY ? u_old : (gptr<const T>)u_out;
 #pragma unroll
@@ -105,7 +107,7 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_row(
     }
     line_fft<N, false>(u, L, t, tw);
     const FieldBuf ub = pair_rows<T, N>(U, r0, 2 * G::LPB);
-    store_pair_halves_b<T, N>(u, L, t, ub, oa, ub, ob);
+    store_pair_halves_b<T, N>(u, L, t, ub, oa, ub, ob, kst);
   }
 }
 
@@ -123,7 +125,7 @@ __global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_sg_col(const cpx
   const int field = tile / tiles_per_field;
   const int col = (tile % tiles_per_field) * WT + c;
   const bool valid = col < ncols;
-  const ColArr<T> Ua(U, field, N, ncols, col, valid, t, G::TL), Sa(S, field, N, ncols, col, valid, t, G::TL),
+  const ColArr<T, true> Ua(U, field, N, ncols, col, valid, t, G::TL), Sa(S, field, N, ncols, col, valid, t, G::TL),
       Wa(W, field, N, ncols, col, valid, t, G::TL);
   cpx<T>* L = lds + c;
   const T kx = kx0 * (T)col;

@@ -188,20 +188,31 @@ struct FieldBuf {
 
 // A column tile's view of one complex array laid out [field][N][ncols]:
 // element s of thread (c, t) is row t + s*TL of column col of the block's
-// field (field must be block-uniform).  Columns past the end get an offset
-// beyond the buffer's range, so their loads read zeros and their stores are
-// dropped by the hardware range check.
-template <typename T>
+// field (field must be block-uniform).  IL: the rows of each pair (2p, 2p+1)
+// are interleaved element by element, (y, x) at (y - y%2) ncols + 2x + y%2,
+// so that W adjacent columns span 2W-element segments.  Columns past the
+// end get an offset beyond the buffer's range, so their loads read zeros and
+// their stores are dropped by the hardware range check.
+template <typename T, bool IL = false>
 struct ColArr {
   FieldBuf b;
   unsigned o0, ds;
+  bool one;  // TL == 1 (interleaved lines of 16 or less): parity of y is that of s
   __device__ ColArr(const void* array, int field, int N, int ncols, int col, bool valid, int t, int TL)
       : b((const char*)array + (size_t)field * N * ncols * sizeof(cpx<T>),
           (unsigned)((size_t)N * ncols * sizeof(cpx<T>))),
-        o0(valid ? (unsigned)(col + t * ncols) * (unsigned)sizeof(cpx<T>) : 0x80000000u),
-        ds((unsigned)(TL * ncols) * (unsigned)sizeof(cpx<T>)) {}
-  __device__ __forceinline__ cpx<T> ld(int s) const { return b.template ldc<T>(o0, s * ds); }
-  __device__ __forceinline__ void st(int s, cpx<T> v) const { b.st(o0, s * ds, v); }
+        o0(!valid ? 0x80000000u
+                  : (unsigned)(IL ? (t & ~1) * ncols + 2 * col + (t & 1) : col + t * ncols) *
+                        (unsigned)sizeof(cpx<T>)),
+        ds((unsigned)(TL * ncols) * (unsigned)sizeof(cpx<T>)),
+        one(IL && TL == 1) {}
+  // TL == 1: y = s, so an odd s is one element past o0 and one row short of s ds
+  __device__ __forceinline__ unsigned voff(int s) const {
+    return one && (s & 1) && o0 != 0x80000000u ? o0 + (unsigned)sizeof(cpx<T>) : o0;
+  }
+  __device__ __forceinline__ unsigned soff(int s) const { return one && (s & 1) ? (s - 1) * ds : s * ds; }
+  __device__ __forceinline__ cpx<T> ld(int s) const { return b.template ldc<T>(voff(s), soff(s)); }
+  __device__ __forceinline__ void st(int s, cpx<T> v) const { b.st(voff(s), soff(s), v); }
 };
 
 // Keeps the compiler from moving memory accesses across this point (used to
@@ -375,17 +386,27 @@ template <typename T, int N>
 __device__ __forceinline__ unsigned pair_row_off(int row_in_block, bool valid) {
   return valid ? (unsigned)(row_in_block * (N / 2 + 1) * (int)sizeof(cpx<T>)) : kNoRow;
 }
+// Offset of row `row_in_block` in the pair-interleaved layout (see ColArr):
+// the pair's base plus one element for the odd row; elements then step by
+// two (kstep = 2 sizeof(cpx<T>) in the pair helpers below).
+template <typename T, int N>
+__device__ __forceinline__ unsigned pair_row_off_il(int row_in_block, bool valid) {
+  return valid ? (unsigned)(((row_in_block & ~1) * (N / 2 + 1) + (row_in_block & 1)) * (int)sizeof(cpx<T>))
+               : kNoRow;
+}
 
-// load_pair_spectrum through buffers: A at byte offset oa, B at ob.
+// load_pair_spectrum through buffers: A at byte offset oa, B at ob, element
+// k at k * kstep bytes further.
 template <typename T, int N>
 __device__ __forceinline__ void load_pair_spectrum_b(cpx<T> (&v)[line_radix(N)], const FieldBuf& A, unsigned oa,
-                                                     const FieldBuf& B, unsigned ob, int t, T scale) {
+                                                     const FieldBuf& B, unsigned ob, int t, T scale,
+                                                     unsigned kstep = sizeof(cpx<T>)) {
   constexpr int TL = N / line_radix(N);
 #pragma unroll
   for (int s = 0; s < line_radix(N); ++s) {
     const int e = t + s * TL;
     const bool lo = e <= N / 2;
-    const unsigned k = (unsigned)(lo ? e : N - e) * (unsigned)sizeof(cpx<T>);
+    const unsigned k = (unsigned)(lo ? e : N - e) * kstep;
     cpx<T> a = A.template ldc<T>(oa + k, 0);
     cpx<T> b = B.template ldc<T>(ob + k, 0);
     if (e == 0 || e == N / 2) {
@@ -400,10 +421,11 @@ __device__ __forceinline__ void load_pair_spectrum_b(cpx<T> (&v)[line_radix(N)],
   }
 }
 
-// store_pair_halves through buffers.
+// store_pair_halves through buffers (element k at k * kstep bytes).
 template <typename T, int N>
 __device__ __forceinline__ void store_pair_halves_b(const cpx<T> (&v)[line_radix(N)], cpx<T>* L, int t,
-                                                    const FieldBuf& A, unsigned oa, const FieldBuf& B, unsigned ob) {
+                                                    const FieldBuf& A, unsigned oa, const FieldBuf& B, unsigned ob,
+                                                    unsigned kstep = sizeof(cpx<T>)) {
   constexpr int R = line_radix(N);
   constexpr int TL = N / R;
   __syncthreads();
@@ -417,7 +439,7 @@ __device__ __forceinline__ void store_pair_halves_b(const cpx<T> (&v)[line_radix
     const cpx<T> zk = L[lds_idx(k)];
     const cpx<T> zm = conj(L[lds_idx((N - k) & (N - 1))]);
     const cpx<T> sum = zk + zm, dif = zk - zm;
-    const unsigned kb = (unsigned)k * (unsigned)sizeof(cpx<T>);
+    const unsigned kb = (unsigned)k * kstep;
     A.st(oa + kb, 0, sum);
     B.st(ob + kb, 0, cpx<T>{dif.im, -dif.re});
   }
