@@ -57,3 +57,31 @@ def test_entry_points_reject_null_plan(lib):
     assert b.lib.fft2d_destroy(None) == b.PST_ERR_INVALID
     assert b.lib.solve_batch(None, -1, None) in (b.PST_ERR_INVALID, b.PST_ERR_UNSUPPORTED)
     assert b.lib.pst_version().decode().startswith("pst")
+
+
+def test_column_variant_table_on_host(lib):
+    # the compiled column tiles follow the stated rules: variant 0 fills 1024
+    # threads / 150 KB of LDS; single-field FP32 passes of 4096 and more add
+    # the 32-values-per-thread split variants; anything else has variant 1 =
+    # half of variant 0's width; unknown variants and sizes are rejected
+    from paper_1206_3215_amd import binding as b
+    assert b.column_variants(b.PST_FP32, 4096, True) == [(4, 16, 0), (4, 32, 1), (4, 16, 1), (8, 32, 1)]
+    assert b.column_variants(b.PST_FP32, 8192, True) == [(2, 16, 0), (2, 32, 1), (2, 16, 1), (4, 32, 1)]
+    assert b.column_variants(b.PST_FP32, 4096, False) == [(4, 16, 0), (2, 16, 0)]
+    assert b.column_variants(b.PST_FP64, 4096, True) == [(2, 16, 0), (1, 16, 0)]
+    assert b.column_variants(b.PST_FP32, 1024, True) == [(16, 16, 0), (8, 16, 0)]
+    assert b.column_variants(b.PST_FP32, 16, True) == [(16, 16, 0), (8, 16, 0)]
+    for prec in (b.PST_FP32, b.PST_FP64):
+        for e in range(2, 14):
+            n = 1 << e
+            for single in (True, False):
+                for w, vpt, split in b.column_variants(prec, n, single):
+                    r = min(n, vpt)
+                    esz = (4 if split else 8) * (2 if prec == b.PST_FP64 else 1)
+                    assert w * (n // r) <= 1024 and w * (n + n // 16) * esz <= 150 * 1024, (prec, n, w, vpt)
+    w = C.c_int()
+    assert b.lib.pst_column_variant_info(b.PST_FP32, 4096, 9, 1, C.byref(w), C.byref(w), C.byref(w)) \
+        == b.PST_ERR_INVALID
+    assert b.lib.pst_column_variant_info(b.PST_FP32, 3000, 0, 1, C.byref(w), C.byref(w), C.byref(w)) \
+        == b.PST_ERR_INVALID
+    assert b.lib.pst_set_column_variant(None, 0) == b.PST_ERR_INVALID
