@@ -318,33 +318,6 @@ inline void allow_lds(K kernel, size_t bytes) {
 // ------------------------------------------------------ real row pairs ---
 // Two real rows a, b travel as one complex line z = a + i b.
 
-// Gather z's spectrum from the half spectra A, B (n/2+1 entries each) of
-// rows a and b: Z[k] = A[k] + i B[k], Z[n-k] = conj(A[k]) + i conj(B[k]).
-// The imaginary parts of the self-conjugate modes k = 0, n/2 are ignored,
-// as an inverse real transform does.  Missing rows read as zero.
-template <typename T, int N>
-__device__ __forceinline__ void load_pair_spectrum(cpx<T> (&v)[line_radix(N)], const cpx<T>* A,
-                                                   const cpx<T>* B, int t, bool va, bool vb,
-                                                   T scale) {
-  constexpr int TL = N / line_radix(N);
-#pragma unroll
-  for (int s = 0; s < line_radix(N); ++s) {
-    const int e = t + s * TL;
-    const bool lo = e <= N / 2;
-    const int k = lo ? e : N - e;
-    cpx<T> a = va ? A[k] : cpx<T>{0, 0};
-    cpx<T> b = vb ? B[k] : cpx<T>{0, 0};
-    if (e == 0 || e == N / 2) {
-      a.im = 0;
-      b.im = 0;
-    }
-    if (!lo) {
-      a = conj(a);
-      b = conj(b);
-    }
-    v[s] = (a + mul_i(b)) * scale;
-  }
-}
 
 // After the forward transform Z of z = a + i b (natural order in v), store
 // 2*A[k] = Z[k] + conj(Z[n-k]) and 2*B[k] = -i (Z[k] - conj(Z[n-k])) for
@@ -395,8 +368,12 @@ __device__ __forceinline__ unsigned pair_row_off_il(int row_in_block, bool valid
                : kNoRow;
 }
 
-// load_pair_spectrum through buffers: A at byte offset oa, B at ob, element
-// k at k * kstep bytes further.
+// Gather z's spectrum from the half spectra A, B (n/2+1 entries each) of
+// rows a and b: Z[k] = A[k] + i B[k], Z[n-k] = conj(A[k]) + i conj(B[k]).
+// The imaginary parts of the self-conjugate modes k = 0, n/2 are ignored,
+// as an inverse real transform does.  Row a starts at byte offset oa of
+// buffer A, row b at ob of B, element k k * kstep bytes further; a missing
+// row (offset kNoRow) reads as zero.
 template <typename T, int N>
 __device__ __forceinline__ void load_pair_spectrum_b(cpx<T> (&v)[line_radix(N)], const FieldBuf& A, unsigned oa,
                                                      const FieldBuf& B, unsigned ob, int t, T scale,
@@ -421,7 +398,8 @@ __device__ __forceinline__ void load_pair_spectrum_b(cpx<T> (&v)[line_radix(N)],
   }
 }
 
-// store_pair_halves through buffers (element k at k * kstep bytes).
+// store_pair_halves through buffers (rows at byte offsets oa, ob; element k
+// k * kstep bytes further; a row at kNoRow is not stored).
 template <typename T, int N>
 __device__ __forceinline__ void store_pair_halves_b(const cpx<T> (&v)[line_radix(N)], cpx<T>* L, int t,
                                                     const FieldBuf& A, unsigned oa, const FieldBuf& B, unsigned ob,
