@@ -15,12 +15,13 @@ TOL = {0: 1e-4, 1: 1e-11}
 D1 = inputs.NS_DOMAIN
 
 
-def gpu_ns(w0, d, dt, nu, nsteps, prec, tol=1e-10, max_iter=50, fixed=0, want_iters=False):
+def gpu_ns(w0, d, dt, nu, nsteps, prec, tol=1e-10, max_iter=50, fixed=0, want_iters=False, variant=0):
     torch = need_gpu()
     from paper_1206_3215_amd import binding as b
     w0 = w0 if w0.ndim == 3 else w0[None]
     batch, ny, nx = w0.shape
     plan = b.Plan(nx, ny, b.PST_R2C, prec, batch)
+    plan.set_column_variant(variant)
     W = to_dev(w0, torch, plan.real_dtype)
     its = torch.zeros(max(nsteps, 1) * batch, dtype=torch.int32, device="cuda")
     plan.ns_step(W, d, dt, nu, nsteps, tol=tol, max_iter=max_iter, fixed_iters=fixed,
@@ -106,11 +107,12 @@ def test_energy_enstrophy(prec):
     assert abs(q[1, 1] / ons.enstrophy(w0[1], 1, 1) - 1) < tq
 
 
-@pytest.mark.parametrize("n", [1024, 2048])
-def test_full_size_random_phase_short(n):
-    # benchmark grids (uneven batch members), FP32, fixed 2 iterations, 4 steps
+@pytest.mark.parametrize("n,variant", [(1024, 0), (1024, 1), (2048, 0), (2048, 1)])
+def test_full_size_random_phase_short(n, variant):
+    # benchmark grids (uneven batch members) in both column variants, FP32,
+    # fixed 2 iterations, 4 steps
     w0 = inputs.ns_random_phase(n, seed=4)
-    got, _, _, _ = gpu_ns(w0, D1, 1e-3, 1e-3, 4, 0, fixed=2)
+    got, _, _, _ = gpu_ns(w0, D1, 1e-3, 1e-3, 4, 0, fixed=2, variant=variant)
     ref, _, _ = ons.run(w0, 1.0, 1.0, 1e-3, 1e-3, 4, fixed_iters=2)
     assert rel_err(got[0], ref) < TOL[0]
 

@@ -12,12 +12,13 @@ pytestmark = pytest.mark.gpu
 TOL = {0: 1e-4, 1: 1e-11}
 
 
-def gpu_sg(u0, v0, d, dt, nsteps, prec, hams=False):
+def gpu_sg(u0, v0, d, dt, nsteps, prec, hams=False, variant=0):
     """Start from (u0, v0) [batch][ny][nx], advance nsteps; returns (u_prev, u_curr, H list)."""
     torch = need_gpu()
     from paper_1206_3215_amd import binding as b
     batch, ny, nx = u0.shape
     plan = b.Plan(nx, ny, b.PST_R2C, prec, batch)
+    plan.set_column_variant(variant)
     U0, V0 = to_dev(u0, torch, plan.real_dtype), to_dev(v0, torch, plan.real_dtype)
     up, uc = torch.empty_like(U0), torch.empty_like(U0)
     plan.sg_start(U0, V0, up, uc, d, dt)
@@ -97,18 +98,20 @@ def test_initial_hamiltonian_closed_form():
     assert abs(h[0] - (A * A * math.pi / 2 + series)) < 1e-12 and h[1] == 0.0
 
 
-def test_batch_of_16_at_2048_alone_vs_batch_bitwise():
-    # Benchmark configuration: 16 seeds of 2048^2 FP32 in one launch.  Sampled
+@pytest.mark.parametrize("variant", [0, 1])
+def test_batch_of_16_at_2048_alone_vs_batch_bitwise(variant):
+    # Benchmark configuration: 16 seeds of 2048^2 FP32 in one launch, in both
+    # column variants (the benchmark runs the autotuner's pick).  Sampled
     # seeds against the oracle (20 steps) and bitwise equal when run alone.
     torch = need_gpu()
     d = inputs.PAPER_DOMAIN
     n, dt, steps = 2048, 0.01, 20
     u0 = np.stack([inputs.sg_gaussian(n, n, d, seed=s)[0] for s in range(16)])
     v0 = np.zeros_like(u0)
-    up, uc, _ = gpu_sg(u0, v0, d, dt, steps, 0)
+    up, uc, _ = gpu_sg(u0, v0, d, dt, steps, 0, variant=variant)
     for s in (0, 11):
         u1 = osg.start(u0[s], v0[s], d.lx, d.ly, dt)
         rp, rc = osg.run(u0[s], u1, d.lx, d.ly, dt, steps)
         assert rel_err(uc[s], rc) < TOL[0]
-    up1, uc1, _ = gpu_sg(u0[11:12], v0[11:12], d, dt, steps, 0)
+    up1, uc1, _ = gpu_sg(u0[11:12], v0[11:12], d, dt, steps, 0, variant=variant)
     assert np.array_equal(uc1[0], uc[11]) and np.array_equal(up1[0], up[11])
