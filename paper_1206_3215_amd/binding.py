@@ -14,6 +14,10 @@ import ctypes as C
 import os
 
 import numpy as np
+# torch first: it brings its HIP runtime, which libpst then binds to (loading
+# libpst first would map a second HIP runtime into the process, and device
+# pointers from one are not usable by the other)
+import torch  # noqa: F401
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpst.so")
 if not os.path.exists(_LIB_PATH):

@@ -280,6 +280,8 @@ pst_status fft2d_destroy(pst_plan plan) {
   for (void* p : plan->owned) hipFree(p);
   for (hipEvent_t e : plan->ev_pool) hipEventDestroy(e);
   if (plan->ws_owned) hipFree(plan->ws);
+  if (plan->ns_host) hipHostFree(plan->ns_host);
+  if (plan->ns_ev) hipEventDestroy(plan->ns_ev);
   delete plan;
   return PST_OK;
 }

@@ -41,6 +41,8 @@ struct pst_plan_s {
   size_t off_spec = 0, off_spec2 = 0, off_spec3 = 0, off_spec4 = 0, off_hyb = 0, off_rowpart = 0,
          off_colpart = 0, off_nsstate = 0;
   int ns_guess = 3;  // predicted fixed-point iterations for the next step
+  int* ns_host = nullptr;       // pinned host copy of the NS done/iteration flags
+  hipEvent_t ns_ev = nullptr;   // recorded after the flags' device-to-host copy
   NlsTables nls;
   // per-pass timing (pst_profile_enable)
   bool prof = false;

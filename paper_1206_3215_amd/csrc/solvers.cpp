@@ -7,8 +7,8 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <memory>
 #include <string>
-#include <thread>
 #include <tuple>
 #include <utility>
 #include <vector>
@@ -274,96 +274,159 @@ static pst_status ns_check(Plan* pl, const pst_ns_params* p, int nsteps) {
 }
 
 // nsteps of the pl->batch vorticity fields addressed by omega.
+// One NS call on a plan as a sequence of phases, so that the host can
+// interleave several plans' steps (solve_batch) or run them back to back
+// (ns_step).  A step: one row pass on w^n, the first column pass (forms q),
+// then the predicted number of further iterations, gated on the device by
+// the per-field convergence flags; the host then reads the flags (pinned
+// copy + event) and adds iterations until every field has converged or
+// max_iter is reached.  Fixed-K mode launches exactly K iterations.
+struct NsStepper {
+  Plan* pl;
+  FieldRef omega;
+  const pst_ns_params* p;
+  int* dev_iters;
+  int* const* fstat;
+  NsPtrs P;
+  NsScalars S;
+  int nx, ny, B, lines, h, Wt, fixed;
+  int *done, *iters;
+  double* resid;
+  double vol, fp_floor;
+  int step = 0, launched = 0;
+
+  NsStepper(Plan* pl_, FieldRef omega_, const pst_ns_params* p_, int* dev_iters_, int* const* fstat_)
+      : pl(pl_), omega(omega_), p(p_), dev_iters(dev_iters_), fstat(fstat_) {
+    nx = pl->nx;
+    ny = pl->ny;
+    B = pl->batch;
+    lines = B * ny;
+    h = nx / 2 + 1;
+    Wt = col_w(pl, ny);
+    P.Q = ws_at(pl, pl->off_spec);
+    P.WN = ws_at(pl, pl->off_spec2);
+    P.DK = ws_at(pl, pl->off_spec3);
+    P.NH = ws_at(pl, pl->off_spec4);
+    P.OUT = ws_at(pl, pl->off_spec4);
+    P.D = ws_at(pl, pl->off_hyb);
+    P.dstride = (size_t)B * ny * h;
+    P.part = static_cast<double*>(ws_at(pl, pl->off_colpart));
+    S.kx0 = 2 * M_PI / p->d.lx;
+    S.ky0 = 2 * M_PI / p->d.ly;
+    S.hnu = 0.5 * p->dt * p->nu;
+    S.qdt = 0.5 * p->dt;
+    S.nscale = 0.5;
+    S.dscale = 1.0 / ((double)nx * ny);
+    S.nx = nx;
+    S.kx_cut = (nx - 1) / 3;
+    S.ky_cut = (ny - 1) / 3;
+    done = static_cast<int*>(ws_at(pl, pl->off_nsstate));
+    iters = done + B;
+    resid = reinterpret_cast<double*>(static_cast<char*>(ws_at(pl, pl->off_nsstate)) +
+                                      ((2 * B * sizeof(int) + 7) & ~(size_t)7));
+    vol = (p->d.lx / nx) * (p->d.ly / ny) / ((double)nx * ny);
+    const double eps = pl->prec == PST_FP32 ? std::ldexp(1.0, -23) : 0.0;
+    fp_floor = (16 * eps) * (16 * eps);
+    fixed = p->fixed_iters;
+  }
+  pst_status row(const int* gate) {
+    prof_begin(pl, PST_PASS_NS_ROW);
+    pst_status r = hip_check(ns_row(pl->P, nx, lines, ny, P.D, P.dstride, (void*)P.NH, gate, pl->tw_x, pl->stream),
+                             "ns row");
+    prof_end(pl);
+    return r;
+  }
+  pst_status col(int mode) {
+    if (mode == 1 || mode == 2) prof_begin(pl, PST_PASS_NS_COL);
+    pst_status r = hip_check(ns_col(pl->P, mode, ny, B, P, S, done, pl->tw_y, Wt, pl->stream), "ns column");
+    if (mode == 1 || mode == 2) prof_end(pl);
+    return r;
+  }
+  pst_status finish(int first) {
+    int* iout = dev_iters ? dev_iters + (size_t)step * B : nullptr;
+    return hip_check(ns_finish(B, h, P.part, vol, p->tol, fp_floor, p->max_iter, fixed, first, done, iters, iout,
+                               resid, pl->dstatus, fstat, pl->stream),
+                     "ns finish");
+  }
+  bool adaptive() const { return fixed <= 0; }
+  // entry: w^n = rfft2(omega), increment 0, derivatives of w^n
+  pst_status begin() {
+    if (adaptive() && pl->ns_host == nullptr) {
+      TRY(hip_check(hipHostMalloc((void**)&pl->ns_host, 2 * B * sizeof(int), hipHostMallocDefault),
+                    "hipHostMalloc(ns flags)"));
+      TRY(hip_check(hipEventCreateWithFlags(&pl->ns_ev, hipEventDisableTiming), "hipEventCreate"));
+    }
+    TRY(hip_check(fft_row_r2c(pl->P, nx, lines, ny, omega, (void*)P.NH, pl->tw_x, pl->stream), "ns entry row"));
+    return col(0);
+  }
+  pst_status iterate() {
+    TRY(row(done));
+    TRY(col(2));
+    TRY(finish(0));
+    ++launched;
+    return PST_OK;
+  }
+  // queue a step's first iteration and its predicted further ones; in
+  // adaptive mode also the flags' copy to the host
+  pst_status start_step() {
+    TRY(row(nullptr));
+    TRY(col(1));
+    TRY(finish(1));
+    launched = 1;
+    const int target = fixed > 0 ? fixed : std::min(std::max(pl->ns_guess, 1), p->max_iter);
+    while (launched < target) TRY(iterate());
+    return adaptive() ? request_flags() : PST_OK;
+  }
+  pst_status request_flags() {
+    TRY(hip_check(hipMemcpyAsync(pl->ns_host, done, 2 * B * sizeof(int), hipMemcpyDeviceToHost, pl->stream),
+                  "read ns flags"));
+    return hip_check(hipEventRecord(pl->ns_ev, pl->stream), "hipEventRecord");
+  }
+  // adaptive mode: wait for the flags; *complete is set when the step has
+  // converged everywhere (or hit max_iter), otherwise one more iteration and
+  // the next flags copy are queued
+  pst_status poll(bool* complete) {
+    TRY(hip_check(hipEventSynchronize(pl->ns_ev), "hipEventSynchronize"));
+    bool all = true;
+    int most = 0;
+    for (int f = 0; f < B; ++f) {
+      all = all && pl->ns_host[f] != 0;
+      most = std::max(most, pl->ns_host[B + f]);
+    }
+    *complete = all || launched >= p->max_iter;
+    if (*complete) {
+      pl->ns_guess = std::max(1, most);
+      return PST_OK;
+    }
+    TRY(iterate());
+    return request_flags();
+  }
+  pst_status end_step() {
+    ++step;
+    return PST_OK;
+  }
+  // exit: omega = irfft2(w^n + d)
+  pst_status end() {
+    TRY(col(3));
+    return hip_check(fft_row_c2r(pl->P, nx, lines, ny, P.OUT, omega, 1.0 / ((double)nx * ny), pl->tw_x, pl->stream),
+                     "ns exit row");
+  }
+};
+
 static pst_status ns_run(Plan* pl, FieldRef omega, const pst_ns_params* p, int nsteps, int* dev_iters,
                          int* const* fstat = nullptr) {
   if (nsteps == 0) return PST_OK;
-  const int nx = pl->nx, ny = pl->ny, B = pl->batch, lines = B * ny, h = nx / 2 + 1;
-  const int Wt = col_w(pl, ny);
-  hipStream_t s = pl->stream;
-  NsPtrs P;
-  P.Q = ws_at(pl, pl->off_spec);
-  P.WN = ws_at(pl, pl->off_spec2);
-  P.DK = ws_at(pl, pl->off_spec3);
-  P.NH = ws_at(pl, pl->off_spec4);
-  P.OUT = ws_at(pl, pl->off_spec4);
-  P.D = ws_at(pl, pl->off_hyb);
-  P.dstride = (size_t)B * ny * h;
-  P.part = static_cast<double*>(ws_at(pl, pl->off_colpart));
-  NsScalars S;
-  S.kx0 = 2 * M_PI / p->d.lx;
-  S.ky0 = 2 * M_PI / p->d.ly;
-  S.hnu = 0.5 * p->dt * p->nu;
-  S.qdt = 0.5 * p->dt;
-  S.nscale = 0.5;
-  S.dscale = 1.0 / ((double)nx * ny);
-  S.nx = nx;
-  S.kx_cut = (nx - 1) / 3;
-  S.ky_cut = (ny - 1) / 3;
-  int* done = static_cast<int*>(ws_at(pl, pl->off_nsstate));
-  int* iters = done + B;
-  double* resid = reinterpret_cast<double*>(static_cast<char*>(ws_at(pl, pl->off_nsstate)) +
-                                            ((2 * B * sizeof(int) + 7) & ~(size_t)7));
-  const double vol = (p->d.lx / nx) * (p->d.ly / ny) / ((double)nx * ny);
-  const double eps = pl->prec == PST_FP32 ? std::ldexp(1.0, -23) : 0.0;
-  const double fp_floor = (16 * eps) * (16 * eps);
-  const int fixed = p->fixed_iters;
-  auto row = [&](const int* gate) {
-    prof_begin(pl, PST_PASS_NS_ROW);
-    pst_status r = hip_check(ns_row(pl->P, nx, lines, ny, P.D, P.dstride, (void*)P.NH, gate, pl->tw_x, s), "ns row");
-    prof_end(pl);
-    return r;
-  };
-  auto col = [&](int mode) {
-    if (mode == 1 || mode == 2) prof_begin(pl, PST_PASS_NS_COL);
-    pst_status r = hip_check(ns_col(pl->P, mode, ny, B, P, S, done, pl->tw_y, Wt, s), "ns column");
-    if (mode == 1 || mode == 2) prof_end(pl);
-    return r;
-  };
-  auto finish = [&](int first, int* iters_out) {
-    return hip_check(ns_finish(B, h, P.part, vol, p->tol, fp_floor, p->max_iter, fixed, first, done, iters,
-                               iters_out, resid, pl->dstatus, fstat, s),
-                     "ns finish");
-  };
-  // entry: w^n = rfft2(omega), increment 0, derivatives of w^n
-  TRY(hip_check(fft_row_r2c(pl->P, nx, lines, ny, omega, (void*)P.NH, pl->tw_x, s), "ns entry row"));
-  TRY(col(0));
-  std::vector<int> hbuf(2 * B);
-  for (int step = 0; step < nsteps; ++step) {
-    int* iout = dev_iters ? dev_iters + (size_t)step * B : nullptr;
-    TRY(row(nullptr));
-    TRY(col(1));
-    TRY(finish(1, iout));
-    int launched = 1;
-    const int target = fixed > 0 ? fixed : std::min(std::max(pl->ns_guess, 1), p->max_iter);
-    while (launched < target) {
-      TRY(row(done));
-      TRY(col(2));
-      TRY(finish(0, iout));
-      ++launched;
+  NsStepper st(pl, omega, p, dev_iters, fstat);
+  TRY(st.begin());
+  for (int k = 0; k < nsteps; ++k) {
+    TRY(st.start_step());
+    if (st.adaptive()) {
+      bool complete = false;
+      while (!complete) TRY(st.poll(&complete));
     }
-    if (fixed > 0) continue;
-    int most = 0;
-    while (true) {
-      TRY(hip_check(hipMemcpyAsync(hbuf.data(), done, 2 * B * sizeof(int), hipMemcpyDeviceToHost, s), "read ns flags"));
-      TRY(hip_check(hipStreamSynchronize(s), "hipStreamSynchronize"));
-      bool all = true;
-      most = 0;
-      for (int f = 0; f < B; ++f) {
-        all = all && hbuf[f] != 0;
-        most = std::max(most, hbuf[B + f]);
-      }
-      if (all || launched >= p->max_iter) break;
-      TRY(row(done));
-      TRY(col(2));
-      TRY(finish(0, iout));
-      ++launched;
-    }
-    pl->ns_guess = std::max(1, most);
+    TRY(st.end_step());
   }
-  // exit: omega = irfft2(w^n + d)
-  TRY(col(3));
-  return hip_check(fft_row_c2r(pl->P, nx, lines, ny, P.OUT, omega, 1.0 / ((double)nx * ny), pl->tw_x, s),
-                   "ns exit row");
+  return st.end();
 }
 
 pst_status ns_step(pst_plan pl, void* omega, const pst_ns_params* p, int nsteps, int* dev_iters) {
@@ -665,42 +728,44 @@ extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stre
     jobs.push_back({gi, bp, adaptive});
   }
   std::vector<hipEvent_t> joins(jobs.size(), nullptr);
-  auto run_group = [&](size_t ji) -> pst_status {
+  // table of a chunk's active requests: f0, f1 and status slots
+  auto upload_table = [&](size_t ji, const std::vector<int>& act, std::vector<uintptr_t>* key) -> pst_status {
+    const std::vector<int>& g = groups[jobs[ji].gi];
+    BatchPlan* bp = jobs[ji].bp;
+    const int cap = bp->pl->batch;
+    std::vector<void*> tab(3 * cap, nullptr);
+    for (size_t a = 0; a < act.size(); ++a) {
+      const pst_request& r = reqs[g[act[a]]];
+      tab[a] = r.f0;
+      tab[cap + a] = r.f1;
+      tab[2 * cap + a] = bp->dfst + act[a];
+      if (key) {
+        key->push_back((uintptr_t)r.f0);
+        key->push_back((uintptr_t)r.f1);
+      }
+    }
+    return hip_check(hipMemcpyAsync(bp->dtab, tab.data(), tab.size() * sizeof(void*), hipMemcpyHostToDevice,
+                                    bp->pl->stream),
+                     "upload field table");
+  };
+  // active requests of a group and the chunk length (smallest remaining count)
+  auto next_chunk = [](const std::vector<int>& left, std::vector<int>* act) {
+    act->clear();
+    int k = 0;
+    for (size_t j = 0; j < left.size(); ++j)
+      if (left[j] > 0) {
+        act->push_back((int)j);
+        k = k == 0 ? left[j] : std::min(k, left[j]);
+      }
+    return k;
+  };
+  // per-request device status, then the group's join event
+  auto close_group = [&](size_t ji) -> pst_status {
     const std::vector<int>& g = groups[jobs[ji].gi];
     BatchPlan* bp = jobs[ji].bp;
     const pst_request& r0 = reqs[g[0]];
-    hipStream_t s = g_side_streams[jobs[ji].gi];
+    hipStream_t s = bp->pl->stream;
     const int cap = bp->pl->batch;
-    std::vector<int> left(g.size());
-    for (size_t j = 0; j < g.size(); ++j) left[j] = reqs[g[j]].nsteps;
-    if (r0.eq == PST_NS) TRY(hip_check(hipMemsetAsync(bp->dfst, 0, cap * sizeof(int), s), "clear status"));
-    while (true) {
-      std::vector<int> act;
-      int k = 0;
-      for (size_t j = 0; j < g.size(); ++j)
-        if (left[j] > 0) {
-          act.push_back((int)j);
-          k = k == 0 ? left[j] : std::min(k, left[j]);
-        }
-      if (act.empty()) break;
-      std::vector<void*> tab(3 * cap, nullptr);
-      std::vector<uintptr_t> key;
-      for (size_t a = 0; a < act.size(); ++a) {
-        const pst_request& r = reqs[g[act[a]]];
-        tab[a] = r.f0;
-        tab[cap + a] = r.f1;
-        tab[2 * cap + a] = bp->dfst + act[a];
-        key.push_back((uintptr_t)r.f0);
-        key.push_back((uintptr_t)r.f1);
-      }
-      key.push_back((uintptr_t)k);
-      key.push_back((uintptr_t)act.size());
-      TRY(hip_check(hipMemcpyAsync(bp->dtab, tab.data(), tab.size() * sizeof(void*), hipMemcpyHostToDevice, s),
-                    "upload field table"));
-      TRY(run_chunk(*bp, r0.eq, r0.params, (int)act.size(), k, !jobs[ji].adaptive, key));
-      for (int a : act) left[a] -= k;
-    }
-    // per-request device status
     std::vector<int*> stp(g.size());
     bool any = false;
     for (size_t j = 0; j < g.size(); ++j) {
@@ -722,33 +787,92 @@ extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stre
     joins[ji] = j;
     return PST_OK;
   };
-  // Fixed-schedule groups first: their launches (graph replays) are
-  // asynchronous.  Adaptive NS groups wait on the host once per step, so
-  // each runs on a host thread of its own and their waits overlap with each
-  // other and with the device work already queued.
+  // fixed-schedule group: chunk after chunk, each a graph replay once seen
+  auto run_fixed = [&](size_t ji) -> pst_status {
+    const std::vector<int>& g = groups[jobs[ji].gi];
+    BatchPlan* bp = jobs[ji].bp;
+    const pst_request& r0 = reqs[g[0]];
+    std::vector<int> left(g.size()), act;
+    for (size_t j = 0; j < g.size(); ++j) left[j] = reqs[g[j]].nsteps;
+    if (r0.eq == PST_NS)
+      TRY(hip_check(hipMemsetAsync(bp->dfst, 0, bp->pl->batch * sizeof(int), bp->pl->stream), "clear status"));
+    for (int k; (k = next_chunk(left, &act)) > 0;) {
+      std::vector<uintptr_t> key;
+      TRY(upload_table(ji, act, &key));
+      key.push_back((uintptr_t)k);
+      key.push_back((uintptr_t)act.size());
+      TRY(run_chunk(*bp, r0.eq, r0.params, (int)act.size(), k, true, key));
+      for (int a : act) left[a] -= k;
+    }
+    return close_group(ji);
+  };
+  // Fixed-schedule groups first: their launches are asynchronous.  Adaptive
+  // NS groups then advance in lockstep, one step of every group at a time:
+  // each group's step is queued on its stream before the host waits for the
+  // first group's convergence flags, so the groups' host round trips and
+  // device work overlap.
   std::vector<size_t> adaptive;
   for (size_t ji = 0; ji < jobs.size() && result == PST_OK; ++ji) {
     if (jobs[ji].adaptive) adaptive.push_back(ji);
-    else result = run_group(ji);
+    else result = run_fixed(ji);
   }
-  if (result == PST_OK && adaptive.size() == 1) {
-    result = run_group(adaptive[0]);
-  } else if (result == PST_OK && !adaptive.empty()) {
-    std::vector<pst_status> st(adaptive.size(), PST_OK);
-    std::vector<std::string> msg(adaptive.size());
-    std::vector<std::thread> th;
-    int dev = 0;
-    hipGetDevice(&dev);
-    for (size_t a = 0; a < adaptive.size(); ++a)
-      th.emplace_back([&, a]() {
-        hipSetDevice(dev);
-        st[a] = run_group(adaptive[a]);
-        if (st[a] != PST_OK) msg[a] = pst_last_error();
-      });
-    for (auto& t : th) t.join();
-    for (size_t a = 0; a < adaptive.size() && result == PST_OK; ++a)
-      if (st[a] != PST_OK) result = fail(st[a], "%s", msg[a].c_str());
+  struct NsGroup {
+    size_t ji;
+    std::vector<int> left, act;
+    int k = 0, kdone = 0, cap = 0;
+    bool in_chunk = false, closed = false;
+    std::unique_ptr<NsStepper> st;
+  };
+  std::vector<NsGroup> ns(adaptive.size());
+  for (size_t a = 0; a < adaptive.size() && result == PST_OK; ++a) {
+    NsGroup& q = ns[a];
+    q.ji = adaptive[a];
+    const std::vector<int>& g = groups[jobs[q.ji].gi];
+    q.left.resize(g.size());
+    for (size_t j = 0; j < g.size(); ++j) q.left[j] = reqs[g[j]].nsteps;
+    q.cap = jobs[q.ji].bp->pl->batch;
+    result = hip_check(hipMemsetAsync(jobs[q.ji].bp->dfst, 0, q.cap * sizeof(int), jobs[q.ji].bp->pl->stream),
+                       "clear status");
   }
+  for (bool busy = true; busy && result == PST_OK;) {
+    busy = false;
+    for (NsGroup& q : ns) {  // queue one step of every open group
+      if (q.closed || result != PST_OK) continue;
+      BatchPlan* bp = jobs[q.ji].bp;
+      const pst_request& r0 = reqs[groups[jobs[q.ji].gi][0]];
+      if (!q.in_chunk) {
+        q.k = next_chunk(q.left, &q.act);
+        if (q.k == 0) {
+          q.closed = true;
+          result = close_group(q.ji);
+          continue;
+        }
+        if ((result = upload_table(q.ji, q.act, nullptr)) != PST_OK) break;
+        bp->pl->batch = (int)q.act.size();  // the chunk's field count, restored at its end
+        FieldRef f0;
+        f0.table = bp->dtab;
+        q.st.reset(new NsStepper(bp->pl, f0, static_cast<const pst_ns_params*>(r0.params), nullptr,
+                                 reinterpret_cast<int* const*>(bp->dtab + 2 * q.cap)));
+        q.in_chunk = true;
+        q.kdone = 0;
+        if ((result = q.st->begin()) != PST_OK) break;
+      }
+      busy = true;
+      if ((result = q.st->start_step()) != PST_OK) break;
+    }
+    for (NsGroup& q : ns) {  // wait for each, adding iterations where needed
+      if (!q.in_chunk || result != PST_OK) continue;
+      for (bool complete = false; !complete && result == PST_OK;) result = q.st->poll(&complete);
+      if (result == PST_OK) result = q.st->end_step();
+      if (result == PST_OK && ++q.kdone == q.k) {
+        result = q.st->end();
+        jobs[q.ji].bp->pl->batch = q.cap;
+        for (int a : q.act) q.left[a] -= q.k;
+        q.in_chunk = false;
+      }
+    }
+  }
+  for (NsGroup& q : ns) jobs[q.ji].bp->pl->batch = q.cap;  // also after an error
   for (hipEvent_t j : joins) {
     if (j == nullptr) continue;
     hipStreamWaitEvent(caller, j, 0);
