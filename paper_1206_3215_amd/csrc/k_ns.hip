@@ -13,9 +13,10 @@
 //
 // Spectral arrays are [field][ny][nx/2+1] complex; "hybrid" arrays hold the
 // same layout transformed along x only.  Per iteration:
-//   row pass (row pairs): 4 derivative hybrids -> C2R_x in pairs
-//       (psi_y, psi_x), (omega_x, omega_y) -> J = psi_y omega_x - psi_x omega_y
-//       -> R2C_x of the two rows' J -> N hybrid (times 2)
+//   row pass (row pairs): each of the 4 derivative hybrids -> C2R_x of the
+//       pair's two rows in one complex transform -> J = psi_y omega_x -
+//       psi_x omega_y for both rows -> R2C_x of the two rows' J -> N hybrid
+//       (times 2)
 //   column pass: FFT_y(N hybrid) -> mask -> update d, residual ->
 //       derivatives i ky psi, i kx w, i kx psi, i ky w of w = w^n + d ->
 //       4 x iFFT_y -> derivative hybrids (scaled for the next C2R_x)
@@ -25,6 +26,11 @@
 namespace pst {
 
 enum { NS_ENTRY = 0, NS_FIRST = 1, NS_ITER = 2, NS_EXIT = 3 };
+
+// 1/x: the hardware reciprocal (about 1 ulp) in single precision, a
+// correctly rounded division in double precision
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
 // A block's lines may span several fields; it may skip its work only when
 // every field it touches has converged (the decision must be block-uniform).
@@ -57,30 +63,42 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_ns_row(
   const FieldBuf d0 = pair_rows<T, N>(D, r0, 2 * G::LPB), d1 = pair_rows<T, N>(D + dstride, r0, 2 * G::LPB),
                  d2 = pair_rows<T, N>(D + 2 * dstride, r0, 2 * G::LPB),
                  d3 = pair_rows<T, N>(D + 3 * dstride, r0, 2 * G::LPB), nh = pair_rows<T, N>(NH, r0, 2 * G::LPB);
-  const unsigned oa = pair_row_off<T, N>(la - r0, va), ob = pair_row_off<T, N>(lb - r0, vb);
-  // Fields of like magnitude share a complex transform: cp = psi_y + i psi_x
-  // and cw = omega_x + i omega_y (packing psi with omega, whose sizes differ
-  // by ~|k|^2, would bury the stream-function derivatives in the vorticity
-  // derivatives' rounding).  Then J = Re(cp * cw).
-  T ja[G::R];
-  cpx<T> cp[G::R], c[G::R];
-  load_pair_spectrum_b<T, N>(cp, d0, oa, d2, oa, t, T(1));
-  line_fft<N, true>(cp, L, t, tw);
+  // the spectral work arrays hold the rows of each pair interleaved (ColArr)
+  const unsigned oa = pair_row_off_il<T, N>(la - r0, va), ob = pair_row_off_il<T, N>(lb - r0, vb);
+  constexpr unsigned kst = 2 * sizeof(cpx<T>);
+  // Each derivative of the pair's two rows shares one complex transform,
+  // z_q = D_q(row a) + i D_q(row b): the same field in both halves, so of
+  // like magnitude (packing psi with omega, whose sizes differ by ~|k|^2,
+  // would bury the stream-function derivatives in the vorticity
+  // derivatives' rounding), and the two rows are adjacent in the
+  // interleaved layout.  Then J_a = Re z0 Re z1 - Re z2 Re z3 and J_b the
+  // same with the imaginary parts, and z = J_a + i J_b is transformed back.
+  cpx<T> p[G::R], u[G::R], w[G::R];
+  // each spectrum load takes an opaque copy of t, so that its per-element
+  // offsets are computed where they are used rather than held in registers
+  // across the transforms
+  auto tk = [&]() {
+    int x = t;
+    asm volatile("" : "+v"(x));
+    return x;
+  };
+  load_pair_spectrum_b<T, N>(u, d0, oa, d0, ob, tk(), T(1), kst);  // psi_y
+  line_fft<N, true>(u, L, t, tw);
   mem_fence_compiler();
-  load_pair_spectrum_b<T, N>(c, d1, oa, d3, oa, t, T(1));
-  line_fft<N, true>(c, L, t, tw);
+  load_pair_spectrum_b<T, N>(w, d1, oa, d1, ob, tk(), T(1), kst);  // omega_x
+  line_fft<N, true>(w, L, t, tw);
 #pragma unroll
-  for (int s = 0; s < G::R; ++s) ja[s] = cp[s].re * c[s].re - cp[s].im * c[s].im;
+  for (int s = 0; s < G::R; ++s) p[s] = cpx<T>{u[s].re * w[s].re, u[s].im * w[s].im};
   mem_fence_compiler();
-  load_pair_spectrum_b<T, N>(cp, d0, ob, d2, ob, t, T(1));
-  line_fft<N, true>(cp, L, t, tw);
+  load_pair_spectrum_b<T, N>(u, d2, oa, d2, ob, tk(), T(1), kst);  // psi_x
+  line_fft<N, true>(u, L, t, tw);
   mem_fence_compiler();
-  load_pair_spectrum_b<T, N>(c, d1, ob, d3, ob, t, T(1));
-  line_fft<N, true>(c, L, t, tw);
+  load_pair_spectrum_b<T, N>(w, d3, oa, d3, ob, tk(), T(1), kst);  // omega_y
+  line_fft<N, true>(w, L, t, tw);
 #pragma unroll
-  for (int s = 0; s < G::R; ++s) c[s] = cpx<T>{ja[s], cp[s].re * c[s].re - cp[s].im * c[s].im};
-  line_fft<N, false>(c, L, t, tw);
-  store_pair_halves_b<T, N>(c, L, t, nh, oa, nh, ob);
+  for (int s = 0; s < G::R; ++s) p[s] = cpx<T>{p[s].re - u[s].re * w[s].re, p[s].im - u[s].im * w[s].im};
+  line_fft<N, false>(p, L, t, tw);
+  store_pair_halves_b<T, N>(p, L, t, nh, oa, nh, ob, kst);
 }
 
 struct NsColArgs {
@@ -111,14 +129,17 @@ __global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_ns_col(const cpx
   const bool valid = col < ncols;
   cpx<T>* L = lds + c;
   // columns past the end read zeros and store nothing (buffer range check)
-  auto arr = [&](const cpx<T>* a) { return ColArr<T>(a, field, MY, ncols, col, valid, t, G::TL); };
+  // work arrays in the pair-interleaved layout; the entry input (omega's
+  // x-transform) and the exit output (read by the inverse real row pass) plain
+  auto arr = [&](const cpx<T>* a) { return ColArr<T, true>(a, field, MY, ncols, col, valid, t, G::TL); };
+  auto plain = [&](const cpx<T>* a) { return ColArr<T, false>(a, field, MY, ncols, col, valid, t, G::TL); };
   cpx<T> w[G::R], v[G::R];
 
   if constexpr (MODE == NS_EXIT) {
 #pragma unroll
     for (int s = 0; s < G::R; ++s) v[s] = arr(WN).ld(s) + arr(DK).ld(s);
     line_fft<MY, true, WT>(v, L, t, tw);
-    const ColArr<T> out = arr(OUT);
+    const ColArr<T> out = plain(OUT);
 #pragma unroll
     for (int s = 0; s < G::R; ++s) out.st(s, v[s]);
     return;
@@ -129,10 +150,10 @@ __global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_ns_col(const cpx
     double res = 0.0, ens = 0.0;
     // N hybrid -> spectrum (entry: omega's x-transform -> w^n)
 #pragma unroll
-    for (int s = 0; s < G::R; ++s) v[s] = arr(NH).ld(s);
+    for (int s = 0; s < G::R; ++s) v[s] = MODE == NS_ENTRY ? plain(NH).ld(s) : arr(NH).ld(s);
     line_fft<MY, false, WT>(v, L, t, tw);
     mem_fence_compiler();
-    const ColArr<T> wna = arr(WN), dka = arr(DK), qa = arr(Q);
+    const ColArr<T, true> wna = arr(WN), dka = arr(DK), qa = arr(Q);
     if constexpr (MODE == NS_ENTRY) {
 #pragma unroll
       for (int s = 0; s < G::R; ++s) {
@@ -186,19 +207,24 @@ __global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_ns_col(const cpx
     const T dsc = (T)a.dscale;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
+      // the per-mode factors are recomputed for every derivative: held in
+      // registers through the four transforms they would push the kernel
+      // past 128 registers (opaque copy of t so they are not hoisted)
+      int tq = t;
+      asm volatile("" : "+v"(tq));
 #pragma unroll
       for (int s = 0; s < G::R; ++s) {
-        const int e = t + s * G::TL;
+        const int e = tq + s * G::TL;
         const int my = e < MY / 2 ? e : e - MY;
         const T ky = (T)(a.ky0 * my);
         const T kyd = (e == MY / 2) ? T(0) : ky;
         const T k2 = kx * kx + ky * ky;
-        const T ik2 = k2 > T(0) ? dsc / k2 : T(0);  // psi_hat = w / |k|^2, psi_hat(0) = 0
+        const T ik2 = k2 > T(0) ? dsc * recip(k2) : T(0);  // psi_hat = w / |k|^2, psi_hat(0) = 0
         const T f = q == 0 ? kyd * ik2 : q == 1 ? kxd * dsc : q == 2 ? kxd * ik2 : kyd * dsc;
         v[s] = mul_i(w[s]) * f;
       }
       line_fft<MY, true, WT>(v, L, t, tw);
-      const ColArr<T> dq = arr(D + q * dstride);
+      const ColArr<T, true> dq = arr(D + q * dstride);
 #pragma unroll
       for (int s = 0; s < G::R; ++s) dq.st(s, v[s]);
       mem_fence_compiler();
