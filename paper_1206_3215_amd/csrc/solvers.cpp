@@ -466,7 +466,8 @@ static pst_status time_col(Plan* pl, pst_eq eq, int w, const void* ptab, float* 
     P.dstride = (size_t)B * ny * h;
     P.part = static_cast<double*>(ws_at(pl, pl->off_colpart));
     NsScalars S{2 * M_PI, 2 * M_PI, 5e-7, 5e-4, 0.5, 1.0 / ((double)nx * ny), nx, (nx - 1) / 3, (ny - 1) / 3};
-    return ns_col(pl->P, 1, ny, B, P, S, static_cast<int*>(ws_at(pl, pl->off_nsstate)), pl->tw_y, w, s);
+    // the iteration pass (mode 2), which runs several times per step
+    return ns_col(pl->P, 2, ny, B, P, S, static_cast<int*>(ws_at(pl, pl->off_nsstate)), pl->tw_y, w, s);
   };
   TRY(hip_check(launch(), "autotune warm-up"));
   hipEvent_t a, b;
