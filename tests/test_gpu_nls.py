@@ -155,3 +155,17 @@ def test_1024_thousand_steps_against_oracle(prec, oracle_1024_1000):
     print(f"prec={prec} rel_err={err:.3e} mass drift={gdiag[-1][0,0]/gdiag[0][0,0]-1:.3e}")
     assert err < TOL[prec]
     assert abs(gdiag[-1][0, 0] / rdiag[-1][1] - 1) < (1e-12 if prec else 1e-4)
+
+
+@pytest.mark.parametrize("n,variant", [(4096, 1), (2048, 1)])
+def test_batched_fields_equal_single_field_runs(n, variant):
+    # several fields per plan at the long-line sizes (one line per block in
+    # the in-place row pass, field index per block): each field bitwise equal
+    # to its own single-field run
+    torch = need_gpu()
+    d = inputs.PAPER_DOMAIN
+    psi0 = np.stack([inputs.nls_gaussian(n, n, d, seed=s) for s in (0, 5)])
+    got, _ = run_gpu(psi0, d, 1e-3, 1.0, 3, 0, variant=variant)
+    for i in range(2):
+        one, _ = run_gpu(psi0[i:i + 1], d, 1e-3, 1.0, 3, 0, variant=variant)
+        assert np.array_equal(got[i], one[0])
