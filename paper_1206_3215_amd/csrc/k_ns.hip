@@ -126,7 +126,10 @@ __global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_ns_col(const cpx
   const int field = tile / tiles_per_field;
   if (MODE == NS_ITER && done[field]) return;  // uniform: a block is one field
   const int col = (tile % tiles_per_field) * WT + c;
-  const bool valid = col < ncols;
+  // Later iterations leave out the Nyquist column x: it lies beyond the 2/3
+  // cut, so N is masked there and the update, the derivatives and the
+  // stored values equal the first iteration's (its residual term is zero)
+  const bool valid = col < (MODE == NS_ITER ? ncols - 1 : ncols);
   cpx<T>* L = lds + c;
   // columns past the end read zeros and store nothing (buffer range check)
   // work arrays in the pair-interleaved layout; the entry input (omega's
@@ -244,8 +247,11 @@ __global__ __launch_bounds__(256) void k_ns_finish(int ncols, const double* part
   const int f = blockIdx.x, t = threadIdx.x;
   if (!first && done[f]) return;
   double r = 0.0, z = 0.0;
+  // after the first iteration the Nyquist column's residual term is zero and
+  // its entry holds the first iteration's; its |w|^2 term is unchanged
+  const int nres = first ? ncols : ncols - 1;
   for (int i = t; i < ncols; i += 256) {
-    r += part[2 * ((size_t)f * ncols + i)];
+    if (i < nres) r += part[2 * ((size_t)f * ncols + i)];
     z += part[2 * ((size_t)f * ncols + i) + 1];
   }
   r = line_sum(red, 0, t, 256, r);
@@ -367,7 +373,8 @@ static hipError_t col(int mode, int ny, int nfields, const NsPtrs& P, const NsSc
     constexpr int WT = decltype(wc)::value;
     using G = ColGeom<T, N, WT>;
     const int ncols = S.nx / 2 + 1;
-    const int tiles = (ncols + WT - 1) / WT;
+    const int nrun = mode == NS_ITER ? ncols - 1 : ncols;  // see k_ns_col
+    const int tiles = (nrun + WT - 1) / WT;
     NsColArgs a{S.kx0, S.ky0, S.hnu, S.qdt, S.nscale, S.dscale, S.nx, S.kx_cut, S.ky_cut};
     auto go = [&](auto kern) {
       allow_lds(kern, G::LDS_BYTES);
