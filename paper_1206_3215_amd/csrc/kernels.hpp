@@ -322,7 +322,8 @@ inline void allow_lds(K kernel, size_t bytes) {
 // After the forward transform Z of z = a + i b (natural order in v), store
 // 2*A[k] = Z[k] + conj(Z[n-k]) and 2*B[k] = -i (Z[k] - conj(Z[n-k])) for
 // k = 0..n/2 (the half spectra of rows a and b, times 2).  Uses the line's
-// LDS buffer; contains block barriers.
+// LDS buffer; contains block barriers, the last one after its LDS reads, so
+// a transform may follow at once.
 template <typename T, int N>
 __device__ __forceinline__ void store_pair_halves(const cpx<T> (&v)[line_radix(N)], cpx<T>* L, int t,
                                                   cpx<T>* A, cpx<T>* B, bool va, bool vb) {
@@ -342,6 +343,7 @@ __device__ __forceinline__ void store_pair_halves(const cpx<T> (&v)[line_radix(N
     if (va) A[k] = sum;
     if (vb) B[k] = cpx<T>{dif.im, -dif.re};
   }
+  __syncthreads();
 }
 
 // Row-pair passes reach half-spectrum rows ([rows][N/2+1] complex) through
@@ -421,6 +423,7 @@ __device__ __forceinline__ void store_pair_halves_b(const cpx<T> (&v)[line_radix
     A.st(oa + kb, 0, sum);
     B.st(ob + kb, 0, cpx<T>{dif.im, -dif.re});
   }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------- N dispatch ---
