@@ -89,9 +89,21 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_row(
       if (vb) u_out[rb + e] = u[s].im;
     }
   }
-  if constexpr (MODE != SG_FINAL) {
-    // S first, from sin(u) in place; u itself is then read back from where
-    // this thread just wrote it (STEP: u_out) or from the input (ENTRY), so
+  if constexpr (MODE == SG_STEP) {
+    // S from a second line array, u kept in registers for U (the kernel's
+    // occupancy is already set above 128 registers, so the second array
+    // costs no waves and saves reading u^{n+1} back)
+    cpx<T> sn[G::R];
+#pragma unroll
+    for (int s = 0; s < G::R; ++s) sn[s] = cpx<T>{sin_of(u[s].re), sin_of(u[s].im)};
+    line_fft<N, false>(sn, L, t, tw);
+    const FieldBuf sb = pair_rows<T, N>(S, r0, 2 * G::LPB);
+    store_pair_halves_b<T, N>(sn, L, t, sb, oa, sb, ob, kst);
+    line_fft<N, false>(u, L, t, tw);
+    const FieldBuf ub = pair_rows<T, N>(U, r0, 2 * G::LPB);
+    store_pair_halves_b<T, N>(u, L, t, ub, oa, ub, ob, kst);
+  } else if constexpr (MODE == SG_ENTRY) {
+    // S first, from sin(u) in place; u is then read again from the input, so
     // only one line array is live at a time.
 #pragma unroll
     for (int s = 0; s < G::R; ++s) u[s] = cpx<T>{sin_of(u[s].re), sin_of(u[s].im)};
@@ -99,11 +111,10 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_row(
     const FieldBuf sb = pair_rows<T, N>(S, r0, 2 * G::LPB);
     store_pair_halves_b<T, N>(u, L, t, sb, oa, sb, ob, kst);
     mem_fence_compiler();
-    gptr<const T> src = MODE == SG_ENTRY ? u_old : (gptr<const T>)u_out;
 #pragma unroll
     for (int s = 0; s < G::R; ++s) {
       const int e = t + s * G::TL;
-      u[s] = cpx<T>{va ? src[ra + e] : T(0), vb ? src[rb + e] : T(0)};
+      u[s] = cpx<T>{va ? u_old[ra + e] : T(0), vb ? u_old[rb + e] : T(0)};
     }
     line_fft<N, false>(u, L, t, tw);
     const FieldBuf ub = pair_rows<T, N>(U, r0, 2 * G::LPB);
