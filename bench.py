@@ -285,12 +285,17 @@ def main():
     ap.add_argument("--prec", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", type=int, default=512, help="requests in the serving mix (0 = skip)")
-    ap.add_argument("--extra", action="store_true",
-                    help="also time sine-Gordon and Navier-Stokes batches and more NLS cases")
+    ap.add_argument("--extra", nargs="?", const="sg,ns,nls", default="",
+                    help="also time sine-Gordon (sg) and Navier-Stokes (ns) batches and more NLS cases (nls); "
+                         "a comma-separated subset, all three when given alone")
     ap.add_argument("--sweep", action="store_true", help="also run the paper's grid sweeps (Tables 2-4)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+    extra = {x for x in args.extra.split(",") if x}
+    if extra - {"sg", "ns", "nls"}:
+        print(f"unknown --extra sections: {sorted(extra - {'sg', 'ns', 'nls'})}", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -376,9 +381,11 @@ def main():
         "mass_rel_drift": float(q1[0, 0] / q0[0, 0] - 1),
         "energy_rel_drift": float(q1[0, 1] / q0[0, 1] - 1),
     }
-    if args.extra:
+    if "sg" in extra:
         out["sine_gordon_2048x16"] = bench_sg(b, inputs)
+    if "ns" in extra:
         out["navier_stokes_uneven"] = bench_ns(b, inputs)
+    if "nls" in extra:
         out["nls_cases"] = bench_nls_cases(b, inputs)
     if args.sweep:
         out["paper_sweep"] = bench_sweep(b, inputs)
