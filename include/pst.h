@@ -215,7 +215,10 @@ const char* pst_version(void);
  *      capped so that two 1024-thread blocks fit a CU;
  *   3: twice the W, 32 values per thread, the split exchange (wider row
  *      segments per block, one block per CU).
- * For every other pass and length, variant 1 is half of variant 0's W.
+ * For every other pass and length, variant 1 is half of variant 0's W;
+ * single-field passes of FP64 lines of 4096 and more add
+ *   2: variant 0's W, 32 values per thread, the split exchange (half the
+ *      threads and half the LDS, so that two blocks share a CU).
  * pst_column_variant_info reports (columns per block, values per thread,
  * split exchange 0/1) of variant for length n; single_field != 0 asks about
  * the single-field passes.  PST_ERR_INVALID if n is not a supported length

@@ -58,7 +58,10 @@ struct ColGeom {
 // values per thread, the split exchange and registers capped for 8 waves
 // per SIMD; and one that widens the row segments a block reads and writes:
 // 3, twice the W with 32 values per thread and the split exchange (variant
-// 0's threads and LDS).  Otherwise variant 1 is half of variant 0's W.
+// 0's threads and LDS).  Otherwise variant 1 is half of variant 0's W, and
+// single-field FP64 passes of 4096 and more add 2, variant 0's W with 32
+// values per thread and the split exchange (half the LDS, two blocks per
+// CU, registers capped for 2 waves per SIMD).
 template <typename T, int N>
 struct ColTiles {
   static constexpr int TL = N / line_radix(N);
@@ -68,6 +71,7 @@ struct ColTiles {
   static constexpr int WMAX = fit(16) ? 16 : fit(8) ? 8 : fit(4) ? 4 : fit(2) ? 2 : 1;
   static constexpr int WALT = WMAX > 1 ? WMAX / 2 : 1;
   static constexpr bool SPLIT1 = std::is_same<T, float>::value && N >= 4096;
+  static constexpr bool SPLIT2 = std::is_same<T, double>::value && N >= 4096;
 };
 
 // W columns per block, VPT values per thread, split exchange, and the
@@ -103,6 +107,12 @@ bool dispatch_col1(int var, F&& f) {
   } else if (var == 1) {
     f(ColCfg<CT::WALT, R, false>{});
     return true;
+  }
+  if constexpr (CT::SPLIT2) {
+    if (var == 2) {
+      f(ColCfg<CT::WMAX, 32, true, 2>{});
+      return true;
+    }
   }
   return false;
 }

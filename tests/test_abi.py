@@ -63,12 +63,16 @@ def test_column_variant_table_on_host(lib):
     # the compiled column tiles follow the stated rules: variant 0 fills 1024
     # threads / 150 KB of LDS; single-field FP32 passes of 4096 and more add
     # the 32-values-per-thread split variants; anything else has variant 1 =
-    # half of variant 0's width; unknown variants and sizes are rejected
+    # half of variant 0's width, and single-field FP64 passes of 4096 and more
+    # add variant 2 (32 values per thread, split); unknown variants and sizes
+    # are rejected
     from paper_1206_3215_amd import binding as b
     assert b.column_variants(b.PST_FP32, 4096, True) == [(4, 16, 0), (4, 32, 1), (4, 16, 1), (8, 32, 1)]
     assert b.column_variants(b.PST_FP32, 8192, True) == [(2, 16, 0), (2, 32, 1), (2, 16, 1), (4, 32, 1)]
     assert b.column_variants(b.PST_FP32, 4096, False) == [(4, 16, 0), (2, 16, 0)]
-    assert b.column_variants(b.PST_FP64, 4096, True) == [(2, 16, 0), (1, 16, 0)]
+    assert b.column_variants(b.PST_FP64, 4096, True) == [(2, 16, 0), (1, 16, 0), (2, 32, 1)]
+    assert b.column_variants(b.PST_FP64, 8192, True) == [(1, 16, 0), (1, 16, 0), (1, 32, 1)]
+    assert b.column_variants(b.PST_FP64, 2048, True) == [(4, 16, 0), (2, 16, 0)]
     assert b.column_variants(b.PST_FP32, 1024, True) == [(16, 16, 0), (8, 16, 0)]
     assert b.column_variants(b.PST_FP32, 16, True) == [(16, 16, 0), (8, 16, 0)]
     for prec in (b.PST_FP32, b.PST_FP64):

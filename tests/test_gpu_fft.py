@@ -73,7 +73,8 @@ def test_autotune_picks_a_compiled_variant(eq, kind, n):
     assert 0 <= v < len(plan.column_variants())
 
 
-@pytest.mark.parametrize("prec,n,batch", [(0, 4096, 1), (0, 8192, 1), (1, 4096, 1), (0, 1024, 3), (0, 64, 2)])
+@pytest.mark.parametrize("prec,n,batch", [(0, 4096, 1), (0, 8192, 1), (1, 4096, 1), (1, 8192, 1), (0, 1024, 3),
+                                          (0, 64, 2)])
 def test_column_variants_agree(prec, n, batch):
     # every variant runs the same radix schedule with the same twiddles;
     # variants with the same values per thread give bit-identical results,
@@ -89,6 +90,8 @@ def test_column_variants_agree(prec, n, batch):
     variants = plan.column_variants()
     if prec == b.PST_FP32 and n >= 4096:
         assert len(variants) == 4 and variants[1][1] == 32 and variants[1][2] == 1
+    if prec == b.PST_FP64 and n >= 4096:
+        assert len(variants) == 3 and variants[2][1] == 32 and variants[2][2] == 1
     ref = None
     for v, (_, vpt, _) in enumerate(variants):
         plan.set_column_variant(v)

@@ -112,7 +112,7 @@ def oracle_4096_10():
     return psi0, ref
 
 
-@pytest.mark.parametrize("prec,variant", [(0, 0), (0, 1), (0, 2), (0, 3), (1, 0), (1, 1)])
+@pytest.mark.parametrize("prec,variant", [(0, 0), (0, 1), (0, 2), (0, 3), (1, 0), (1, 1), (1, 2)])
 def test_headline_size_against_oracle_short(prec, variant, oracle_4096_10):
     # 4096^2 on [-5pi,5pi)^2, 10 steps, in every column variant (the
     # benchmark runs the one the autotuner picks).
@@ -122,15 +122,14 @@ def test_headline_size_against_oracle_short(prec, variant, oracle_4096_10):
     assert rel_err(got, ref) < TOL[prec]
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_plane_wave_closed_form_8192(prec):
+@pytest.mark.parametrize("prec,variant", [(0, 1), (1, 0), (1, 2)])
+def test_plane_wave_closed_form_8192(prec, variant):
     # the largest compiled line length (32 values per thread and the split
-    # exchange in FP32 rows and columns)
+    # exchange in rows and in FP32 columns; FP64 columns in variants 0 and 2)
     n, L, A, dt, steps = 8192, 10 * math.pi, 0.3, 1e-3, 20
     X, Y = inputs.grid(n, n, inputs.Domain(L, L, 0, 0))
     k = 2 * math.pi * np.array([-7, 4]) / L
     psi0 = A * np.exp(1j * (k[0] * X + k[1] * Y))
-    variant = 1 if prec == 0 else 0
     got, _ = run_gpu(psi0, inputs.Domain(L, L, 0, 0), dt, 1.0, steps, prec, variant=variant)
     exact = psi0 * np.exp(-1j * (k @ k + A * A) * dt * steps)
     assert rel_err(got, exact) < TOL[prec]
