@@ -346,6 +346,7 @@ __global__ __launch_bounds__(256) void k_ns_cq_finish(int ncols, const double* p
 template <typename T>
 static hipError_t row(int nx, int nlines, int ny, const void* D, size_t dstride, void* NH, const int* done,
                       const void* tw, hipStream_t s) {
+  if (nlines % 2 != 0) return hipErrorInvalidValue;  // the kernel takes rows in pairs
   bool ok = dispatch_n(nx, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
     using G = RowGeom<T, N>;

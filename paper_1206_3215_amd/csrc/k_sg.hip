@@ -44,8 +44,9 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_row(
   cpx<T>* L = lds + lid * lds_line_stride<T>(N);
   const int r0 = 2 * blockIdx.x * G::LPB;
   // U, S, W hold the rows of each pair interleaved (see ColArr)
-  const unsigned oa = pair_row_off_il<T, N>(la - r0, va), ob = pair_row_off_il<T, N>(lb - r0, vb);
-  constexpr unsigned kst = 2 * sizeof(cpx<T>);
+  // (line counts are even: rows a and b of a pair are present together, and
+  // the interleaved layout puts their elements side by side from oa)
+  const unsigned oa = pair_row_off_il<T, N>(la - r0, va && vb);
   // rows a, b are rows y, y+1 of field f; offsets are relative to each field
   const int f = la >> lny;
   const size_t ra = (size_t)(la & ((1 << lny) - 1)) * N, rb = ra + N;
@@ -68,7 +69,7 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_row(
     }
   } else {
     const FieldBuf wb = pair_rows<T, N>(W, r0, 2 * G::LPB);
-    load_pair_spectrum_b<T, N>(u, wb, oa, wb, ob, t, T(1), kst);
+    load_pair_spectrum_il<T, N>(u, wb, oa, t, T(1));
     line_fft<N, true>(u, L, t, tw);
     mem_fence_compiler();
 #pragma unroll
@@ -98,10 +99,10 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_row(
     for (int s = 0; s < G::R; ++s) sn[s] = cpx<T>{sin_of(u[s].re), sin_of(u[s].im)};
     line_fft<N, false>(sn, L, t, tw);
     const FieldBuf sb = pair_rows<T, N>(S, r0, 2 * G::LPB);
-    store_pair_halves_b<T, N>(sn, L, t, sb, oa, sb, ob, kst);
+    store_pair_halves_il<T, N>(sn, L, t, sb, oa);
     line_fft<N, false>(u, L, t, tw);
     const FieldBuf ub = pair_rows<T, N>(U, r0, 2 * G::LPB);
-    store_pair_halves_b<T, N>(u, L, t, ub, oa, ub, ob, kst);
+    store_pair_halves_il<T, N>(u, L, t, ub, oa);
   } else if constexpr (MODE == SG_ENTRY) {
     // S first, from sin(u) in place; u is then read again from the input, so
     // only one line array is live at a time.
@@ -109,7 +110,7 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_row(
     for (int s = 0; s < G::R; ++s) u[s] = cpx<T>{sin_of(u[s].re), sin_of(u[s].im)};
     line_fft<N, false>(u, L, t, tw);
     const FieldBuf sb = pair_rows<T, N>(S, r0, 2 * G::LPB);
-    store_pair_halves_b<T, N>(u, L, t, sb, oa, sb, ob, kst);
+    store_pair_halves_il<T, N>(u, L, t, sb, oa);
     mem_fence_compiler();
 #pragma unroll
     for (int s = 0; s < G::R; ++s) {
@@ -118,7 +119,7 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_row(
     }
     line_fft<N, false>(u, L, t, tw);
     const FieldBuf ub = pair_rows<T, N>(U, r0, 2 * G::LPB);
-    store_pair_halves_b<T, N>(u, L, t, ub, oa, ub, ob, kst);
+    store_pair_halves_il<T, N>(u, L, t, ub, oa);
   }
 }
 
@@ -285,6 +286,7 @@ template <typename T>
 static hipError_t row(int mode, int nx, int nlines, int ny, const void* W, FieldRef u_old, FieldRef d_old,
                       double alpha, FieldRef u_out, FieldRef d_out, FieldRef prev_out, void* U, void* S,
                       const void* tw, hipStream_t s) {
+  if (nlines % 2 != 0) return hipErrorInvalidValue;  // the kernels take rows in pairs
   bool ok = dispatch_n(nx, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
     using G = RowGeom<T, N>;

@@ -194,6 +194,27 @@ struct FieldBuf {
   __device__ __forceinline__ cpx<T> ldc(unsigned voff, unsigned soff) const {
     return ld((cpx<T>*)nullptr, voff, soff);
   }
+  // two adjacent complex values (one 16-byte access in FP32)
+  __device__ __forceinline__ void ld2(unsigned voff, cpx<float>& a, cpx<float>& b) const {
+    using V = float __attribute__((ext_vector_type(4)));
+    const V x = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0));
+    a = {x.x, x.y};
+    b = {x.z, x.w};
+  }
+  __device__ __forceinline__ void ld2(unsigned voff, cpx<double>& a, cpx<double>& b) const {
+    a = ld((cpx<double>*)nullptr, voff, 0);
+    b = ld((cpx<double>*)nullptr, voff, (unsigned)sizeof(cpx<double>));
+  }
+  __device__ __forceinline__ void st2(unsigned voff, cpx<float> a, cpx<float> b) const {
+    using V = float __attribute__((ext_vector_type(4)));
+    using U = unsigned __attribute__((ext_vector_type(4)));
+    const V x = {a.re, a.im, b.re, b.im};
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, x), r, voff, 0, 0);
+  }
+  __device__ __forceinline__ void st2(unsigned voff, cpx<double> a, cpx<double> b) const {
+    st(voff, 0, a);
+    st(voff, (unsigned)sizeof(cpx<double>), b);
+  }
 };
 
 // A column tile's view of one complex array laid out [field][N][ncols]:
@@ -410,6 +431,32 @@ __device__ __forceinline__ void load_pair_spectrum_b(cpx<T> (&v)[line_radix(N)],
   }
 }
 
+// load_pair_spectrum_b for a pair stored interleaved (element k of rows a
+// and b side by side at byte offset o + 2k sizeof(cpx<T>); both rows present,
+// or o = kNoRow for neither): one access per element pair.
+template <typename T, int N>
+__device__ __forceinline__ void load_pair_spectrum_il(cpx<T> (&v)[line_radix(N)], const FieldBuf& A, unsigned o,
+                                                      int t, T scale) {
+  constexpr int TL = N / line_radix(N);
+  constexpr unsigned kstep = 2 * sizeof(cpx<T>);
+#pragma unroll
+  for (int s = 0; s < line_radix(N); ++s) {
+    const int e = t + s * TL;
+    const bool lo = e <= N / 2;
+    cpx<T> a, b;
+    A.ld2(o + (unsigned)(lo ? e : N - e) * kstep, a, b);
+    if (e == 0 || e == N / 2) {
+      a.im = 0;
+      b.im = 0;
+    }
+    if (!lo) {
+      a = conj(a);
+      b = conj(b);
+    }
+    v[s] = (a + mul_i(b)) * scale;
+  }
+}
+
 // store_pair_halves through buffers (rows at byte offsets oa, ob; element k
 // k * kstep bytes further; a row at kNoRow is not stored).
 template <typename T, int N>
@@ -432,6 +479,30 @@ __device__ __forceinline__ void store_pair_halves_b(const cpx<T> (&v)[line_radix
     const unsigned kb = (unsigned)k * kstep;
     A.st(oa + kb, 0, sum);
     B.st(ob + kb, 0, cpx<T>{dif.im, -dif.re});
+  }
+  __syncthreads();
+}
+
+// store_pair_halves_b for a pair stored interleaved (see
+// load_pair_spectrum_il): one access per element pair.
+template <typename T, int N>
+__device__ __forceinline__ void store_pair_halves_il(const cpx<T> (&v)[line_radix(N)], cpx<T>* L, int t,
+                                                     const FieldBuf& A, unsigned o) {
+  constexpr int R = line_radix(N);
+  constexpr int TL = N / R;
+  constexpr unsigned kstep = 2 * sizeof(cpx<T>);
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < R; ++s) L[lds_idx(t + s * TL)] = v[s];
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s <= R / 2; ++s) {
+    if (s == R / 2 && t != 0) break;
+    const int k = (s < R / 2) ? t + s * TL : N / 2;
+    const cpx<T> zk = L[lds_idx(k)];
+    const cpx<T> zm = conj(L[lds_idx((N - k) & (N - 1))]);
+    const cpx<T> sum = zk + zm, dif = zk - zm;
+    A.st2(o + (unsigned)k * kstep, sum, cpx<T>{dif.im, -dif.re});
   }
   __syncthreads();
 }
