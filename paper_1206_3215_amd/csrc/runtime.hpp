@@ -42,6 +42,7 @@ struct pst_plan_s {
          off_colpart = 0, off_nsstate = 0;
   int ns_guess = 3;  // predicted fixed-point iterations for the next step
   int* ns_host = nullptr;       // pinned host copy of the NS done/iteration flags
+  int ns_host_n = 0;            // ints ns_host holds (2 per field of the largest batch seen)
   hipEvent_t ns_ev = nullptr;   // recorded after the flags' device-to-host copy
   NlsTables nls;
   // per-pass timing (pst_profile_enable)

@@ -351,10 +351,21 @@ struct NsStepper {
   bool adaptive() const { return fixed <= 0; }
   // entry: w^n = rfft2(omega), increment 0, derivatives of w^n
   pst_status begin() {
-    if (adaptive() && pl->ns_host == nullptr) {
-      TRY(hip_check(hipHostMalloc((void**)&pl->ns_host, 2 * B * sizeof(int), hipHostMallocDefault),
-                    "hipHostMalloc(ns flags)"));
-      TRY(hip_check(hipEventCreateWithFlags(&pl->ns_ev, hipEventDisableTiming), "hipEventCreate"));
+    if (adaptive()) {
+      // a cached batch plan can run a larger group than the one that first
+      // sized the flags' copy (every earlier copy has been waited for)
+      if (pl->ns_host_n < 2 * B) {
+        if (pl->ns_host != nullptr) {
+          TRY(hip_check(hipHostFree(pl->ns_host), "hipHostFree(ns flags)"));
+          pl->ns_host = nullptr;
+          pl->ns_host_n = 0;
+        }
+        TRY(hip_check(hipHostMalloc((void**)&pl->ns_host, 2 * B * sizeof(int), hipHostMallocDefault),
+                      "hipHostMalloc(ns flags)"));
+        pl->ns_host_n = 2 * B;
+      }
+      if (pl->ns_ev == nullptr)
+        TRY(hip_check(hipEventCreateWithFlags(&pl->ns_ev, hipEventDisableTiming), "hipEventCreate"));
     }
     TRY(hip_check(fft_row_r2c(pl->P, nx, lines, ny, omega, (void*)P.NH, pl->tw_x, pl->stream), "ns entry row"));
     return col(0);

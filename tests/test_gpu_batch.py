@@ -85,6 +85,26 @@ def test_uneven_ns_batch_bitwise_vs_alone():
     assert np.array_equal(to_host(ts[1]), ref)
 
 
+def test_adaptive_ns_group_larger_than_the_first_on_a_cached_plan():
+    # A group of 3 sizes an internal plan for 4 fields; a later group of 4 of
+    # the same class runs on that plan, with more convergence flags to copy
+    # back each step than the first group had.
+    torch = need_gpu()
+    from paper_1206_3215_amd import binding as b
+    fields = [inputs.ns_random_phase(64, seed=s) for s in range(4)]
+    pr = b.make_params("ns", D_NS, 1e-3, nu=1e-3, tol=1e-10)
+    first = [to_dev(f, torch, torch.float64) for f in fields[:3]]
+    b.solve_batch([{"eq": "ns", "f0": t, "params": pr, "nsteps": 2} for t in first])
+    ts = [to_dev(f, torch, torch.float64) for f in fields]
+    st = [torch.full((1,), -1, dtype=torch.int32, device="cuda") for _ in ts]
+    b.solve_batch([{"eq": "ns", "f0": t, "params": pr, "nsteps": 2, "dev_status": s} for t, s in zip(ts, st)])
+    torch.cuda.synchronize()
+    assert all(int(s.item()) == 0 for s in st)
+    for i in (0, 3):
+        ref, _ = single("ns", fields[i], None, {"dt": 1e-3, "nu": 1e-3, "tol": 1e-10}, 2, 1)
+        assert rel_err(to_host(ts[i]), ref) < 1e-12, i
+
+
 def test_repeat_call_replays_graph_and_matches_double_steps():
     torch = need_gpu()
     from paper_1206_3215_amd import binding as b
