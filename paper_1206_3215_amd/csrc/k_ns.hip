@@ -41,7 +41,7 @@ __device__ __forceinline__ bool fields_done(const int* done, int f0, int f1) {
 }
 
 template <typename T, int N>
-__global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_ns_row(
+__global__ __launch_bounds__((RowGeom<T, N>::THREADS)) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && N == 2048 ? 3 : 1))) void k_ns_row(
     const cpx<T>* D, size_t dstride, cpx<T>* NH, int nlines, int ny, const int* done,
     const cpx<T>* __restrict__ tw) {
   using G = RowGeom<T, N>;
@@ -64,8 +64,9 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_ns_row(
                  d2 = pair_rows<T, N>(D + 2 * dstride, r0, 2 * G::LPB),
                  d3 = pair_rows<T, N>(D + 3 * dstride, r0, 2 * G::LPB), nh = pair_rows<T, N>(NH, r0, 2 * G::LPB);
   // the spectral work arrays hold the rows of each pair interleaved (ColArr)
-  const unsigned oa = pair_row_off_il<T, N>(la - r0, va), ob = pair_row_off_il<T, N>(lb - r0, vb);
-  constexpr unsigned kst = 2 * sizeof(cpx<T>);
+  // (line counts are even: rows a and b of a pair are present together, and
+  // the interleaved layout puts their elements side by side from oa)
+  const unsigned oa = pair_row_off_il<T, N>(la - r0, va && vb);
   // Each derivative of the pair's two rows shares one complex transform,
   // z_q = D_q(row a) + i D_q(row b): the same field in both halves, so of
   // like magnitude (packing psi with omega, whose sizes differ by ~|k|^2,
@@ -82,23 +83,23 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_ns_row(
     asm volatile("" : "+v"(x));
     return x;
   };
-  load_pair_spectrum_b<T, N>(u, d0, oa, d0, ob, tk(), T(1), kst);  // psi_y
+  load_pair_spectrum_il<T, N>(u, d0, oa, tk(), T(1));  // psi_y
   line_fft<N, true>(u, L, t, tw);
   mem_fence_compiler();
-  load_pair_spectrum_b<T, N>(w, d1, oa, d1, ob, tk(), T(1), kst);  // omega_x
+  load_pair_spectrum_il<T, N>(w, d1, oa, tk(), T(1));  // omega_x
   line_fft<N, true>(w, L, t, tw);
 #pragma unroll
   for (int s = 0; s < G::R; ++s) p[s] = cpx<T>{u[s].re * w[s].re, u[s].im * w[s].im};
   mem_fence_compiler();
-  load_pair_spectrum_b<T, N>(u, d2, oa, d2, ob, tk(), T(1), kst);  // psi_x
+  load_pair_spectrum_il<T, N>(u, d2, oa, tk(), T(1));  // psi_x
   line_fft<N, true>(u, L, t, tw);
   mem_fence_compiler();
-  load_pair_spectrum_b<T, N>(w, d3, oa, d3, ob, tk(), T(1), kst);  // omega_y
+  load_pair_spectrum_il<T, N>(w, d3, oa, tk(), T(1));  // omega_y
   line_fft<N, true>(w, L, t, tw);
 #pragma unroll
   for (int s = 0; s < G::R; ++s) p[s] = cpx<T>{p[s].re - u[s].re * w[s].re, p[s].im - u[s].im * w[s].im};
   line_fft<N, false>(p, L, t, tw);
-  store_pair_halves_b<T, N>(p, L, t, nh, oa, nh, ob, kst);
+  store_pair_halves_il<T, N>(p, L, t, nh, oa);
 }
 
 struct NsColArgs {
