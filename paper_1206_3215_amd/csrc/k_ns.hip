@@ -40,8 +40,17 @@ __device__ __forceinline__ bool fields_done(const int* done, int f0, int f1) {
   return true;
 }
 
+// Row pass.  FP32 lines of 2048 are held to 3 waves per SIMD (168
+// registers): the 16-byte pair loads would otherwise take the kernel just
+// past that and cost a wave; at this length the cap needs no spills (other
+// lengths would spill, and run uncapped).
 template <typename T, int N>
-__global__ __launch_bounds__((RowGeom<T, N>::THREADS)) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && N == 2048 ? 3 : 1))) void k_ns_row(
+constexpr int ns_row_waves() {
+  return sizeof(T) == 4 && N == 2048 ? 3 : 1;
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__((RowGeom<T, N>::THREADS)) __attribute__((amdgpu_waves_per_eu(ns_row_waves<T, N>()))) void k_ns_row(
     const cpx<T>* D, size_t dstride, cpx<T>* NH, int nlines, int ny, const int* done,
     const cpx<T>* __restrict__ tw) {
   using G = RowGeom<T, N>;
