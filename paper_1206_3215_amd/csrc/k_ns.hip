@@ -138,8 +138,9 @@ __global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_ns_col(const cpx
   const int col = (tile % tiles_per_field) * WT + c;
   // Later iterations leave out the Nyquist column x: it lies beyond the 2/3
   // cut, so N is masked there and the update, the derivatives and the
-  // stored values equal the first iteration's (its residual term is zero)
-  const bool valid = col < (MODE == NS_ITER ? ncols - 1 : ncols);
+  // stored values equal the first iteration's (its residual term is zero);
+  // the first iteration runs it at the end of the field's first tile
+  const bool valid = col < (MODE == NS_ITER || MODE == NS_FIRST ? ncols - 1 : ncols);
   cpx<T>* L = lds + c;
   // columns past the end read zeros and store nothing (buffer range check)
   // work arrays in the pair-interleaved layout; the entry input (omega's
@@ -241,6 +242,78 @@ __global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_ns_col(const cpx
 #pragma unroll
       for (int s = 0; s < G::R; ++s) dq.st(s, v[s]);
       mem_fence_compiler();
+    }
+    if constexpr (MODE == NS_FIRST) {
+      // A field's first tile also carries the x-Nyquist column (lane c = 0),
+      // so that a field takes nx/2 / W tiles: N is masked there and both
+      // x-derivatives vanish, so the column needs the update and two
+      // inverse transforms, the same arithmetic as a tile of its own.
+      if (tile % tiles_per_field == 0) {  // block-uniform
+        // (its addressing is derived from an opaque copy of t after a
+        // compiler fence, so none of it is computed early and held through
+        // the transforms above)
+        mem_fence_compiler();
+        int tn = t;
+        asm volatile("" : "+v"(tn));
+        const int nh = ncols - 1;
+        const bool pk = c == 0;
+        const ColArr<T, true> wnn(WN, field, MY, ncols, nh, pk, tn, G::TL),
+            dkn(DK, field, MY, ncols, nh, pk, tn, G::TL), qn(Q, field, MY, ncols, nh, pk, tn, G::TL);
+        const T kxn = (T)(a.kx0 * nh);
+        const T hnu = (T)a.hnu;
+        double resn = 0.0, ensn = 0.0;
+#pragma unroll
+        for (int s = 0; s < G::R; ++s) {
+          const int e = tn + s * G::TL;
+          const int my = e < MY / 2 ? e : e - MY;
+          const T ky = (T)(a.ky0 * my);
+          const T h = hnu * (kxn * kxn + ky * ky);
+          if (s % 4 == 0) mem_fence_compiler();  // at most four values' loads in flight
+          const cpx<T> wn = wnn.ld(s) + dkn.ld(s);
+          const cpx<T> q = cpx<T>{T(-2) * h * wn.re, T(-2) * h * wn.im};
+          wnn.st(s, wn);
+          qn.st(s, q);
+          const T inv = T(1) / (T(1) + h);
+          const cpx<T> dnew = cpx<T>{q.re * inv, q.im * inv};
+          dkn.st(s, dnew);
+          resn += (double)dnew.re * dnew.re + (double)dnew.im * dnew.im;
+          w[s] = wn + dnew;
+          ensn += (double)w[s].re * w[s].re + (double)w[s].im * w[s].im;
+        }
+        resn = line_sum(red, c, t, G::TL, resn);
+        ensn = line_sum(red, c, t, G::TL, ensn);
+        if (pk && t == 0) {
+          part[2 * ((size_t)field * ncols + nh)] = resn;
+          part[2 * ((size_t)field * ncols + nh) + 1] = ensn;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const ColArr<T, true> dq(D + q * dstride, field, MY, ncols, nh, pk, tn, G::TL);
+          if (q == 1 || q == 2) {
+#pragma unroll
+            for (int s = 0; s < G::R; ++s) dq.st(s, cpx<T>{0, 0});
+            continue;
+          }
+          // (factors recomputed per derivative from an opaque copy of t, as
+          // in the main loop, so they are not held through the transform)
+          int tq = tn;
+          asm volatile("" : "+v"(tq));
+#pragma unroll
+          for (int s = 0; s < G::R; ++s) {
+            const int e = tq + s * G::TL;
+            const int my = e < MY / 2 ? e : e - MY;
+            const T ky = (T)(a.ky0 * my);
+            const T kyd = (e == MY / 2) ? T(0) : ky;
+            const T k2 = kxn * kxn + ky * ky;
+            const T ik2 = k2 > T(0) ? dsc * recip(k2) : T(0);
+            v[s] = mul_i(w[s]) * (q == 0 ? kyd * ik2 : kyd * dsc);
+          }
+          line_fft<MY, true, WT>(v, L, t, tw);
+#pragma unroll
+          for (int s = 0; s < G::R; ++s) dq.st(s, v[s]);
+          mem_fence_compiler();
+        }
+      }
     }
   }
 }
@@ -384,7 +457,7 @@ static hipError_t col(int mode, int ny, int nfields, const NsPtrs& P, const NsSc
     constexpr int WT = decltype(wc)::value;
     using G = ColGeom<T, N, WT>;
     const int ncols = S.nx / 2 + 1;
-    const int nrun = mode == NS_ITER ? ncols - 1 : ncols;  // see k_ns_col
+    const int nrun = mode == NS_ITER || mode == NS_FIRST ? ncols - 1 : ncols;  // see k_ns_col
     const int tiles = (nrun + WT - 1) / WT;
     NsColArgs a{S.kx0, S.ky0, S.hnu, S.qdt, S.nscale, S.dscale, S.nx, S.kx_cut, S.ky_cut};
     auto go = [&](auto kern) {
