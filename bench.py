@@ -1,6 +1,7 @@
 """Benchmark: 2D NLS split-step at 4096^2 (complex64) on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32|fp64] [--no-cpu-baseline]
+                    [--serve COUNT] [--extra [sg,ns,nls]] [--sweep]
 
 Workload: the headline NLS configuration -- a 4096^2 periodic grid on
 [-5pi,5pi)^2, psi0 = 0.5 exp(-r^2) (1 + 0.01 xi) with seeded noise xi,
@@ -11,8 +12,11 @@ timed region starts.
 
 Prints one JSON line with the throughput in grid-point-steps/s, a roofline
 entry for the dominant kernel (its average launch duration measured with HIP
-events on the plan's stream during a second timed run), and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+events on the plan's stream during a second timed run), the serving mix's
+p50/p99 latency against the plain one-request-at-a-time path, and the FP64
+CPU oracle timed on a bounded sample of the same workload together with the
+device field's deviation from it after the same steps.  Progress lines for
+finished sections go to stderr.
 """
 from __future__ import annotations
 
