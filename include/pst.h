@@ -25,9 +25,10 @@
  *    where a function says it synchronises.  Argument errors are detected on
  *    the host before anything is launched and return PST_ERR_INVALID or
  *    PST_ERR_UNSUPPORTED with a message in pst_last_error().  Conditions
- *    found on the device (a non-finite conserved quantity, a fixed-point
- *    iteration that did not converge) are latched in a device status word
- *    read by pst_sync_status().
+ *    found on the device (a non-finite conserved quantity, a field that
+ *    nls_step, sg_step or ns_step left non-finite, a fixed-point iteration
+ *    that did not converge) are latched in a device status word read by
+ *    pst_sync_status().
  *  - Plans are not thread safe; use one plan per stream.  No C++ exception
  *    crosses this interface.
  *  - Supported sizes: nx, ny powers of two in [4, 8192]; batch >= 1.
@@ -48,7 +49,7 @@ typedef enum {
   PST_ERR_OOM = 3,           /* device allocation failed */
   PST_ERR_DEVICE = 4,        /* a HIP runtime call failed */
   PST_ERR_NOT_CONVERGED = 5, /* Navier-Stokes fixed point hit max_iter */
-  PST_ERR_NONFINITE = 6      /* a reduction met Inf/NaN */
+  PST_ERR_NONFINITE = 6      /* a reduction or a solver's result met Inf/NaN */
 } pst_status;
 
 typedef enum { PST_FP32 = 0, PST_FP64 = 1 } pst_prec;
@@ -174,9 +175,16 @@ pst_status pst_sync_status(pst_plan plan, pst_status* device_status);
 /* -------------------------------------------------------------- batching -- */
 
 /* One simulation advanced by solve_batch.  f0/f1 are the caller's device
- * fields: NLS psi (f1 unused); SG (u_prev, u_curr); NS omega (f1 unused).
- * params points to the equation's parameter struct.  dev_status, if not
- * NULL, is a device int receiving this request's pst_status. */
+ * fields (256-byte aligned): NLS psi (f1 unused); SG (u_prev, u_curr); NS
+ * omega (f1 unused).  params points to the equation's parameter struct.
+ * dev_status, if not NULL, is a device int receiving this request's status
+ * when the call's work completes: PST_ERR_NONFINITE if the field holds a
+ * non-finite value at the end of a chunk of steps (or, for NS, a fixed-point
+ * residual is not finite), else PST_ERR_NOT_CONVERGED if an NS step reached
+ * max_iter, else PST_OK.  A failure already held in *dev_status (left by an
+ * earlier call) is kept unless this call finds a worse one (NONFINITE
+ * outranks NOT_CONVERGED); any other value is overwritten.  Zero it before
+ * a simulation's first call. */
 typedef struct {
   pst_eq eq;
   int nx, ny;
@@ -189,11 +197,26 @@ typedef struct {
 } pst_request;
 
 /* Advance n independent simulations, each by its own nsteps, on
- * hip_stream.  Requests are grouped by (equation, nx, ny, precision);
- * every group advances in one launch per pass regardless of how many
- * simulations it holds.  A request's result does not depend on which other
- * requests share the call. */
+ * hip_stream (not a batched form of anything in the paper, whose programs
+ * run one simulation each).  Requests are grouped by (equation, nx, ny,
+ * precision, parameters); every group advances in one launch per pass
+ * regardless of how many simulations it holds.  A request's result does not
+ * depend on which other requests share the call, and one request's failure
+ * (non-finite field, non-convergence) does not alter another's result.
+ * Asynchronous on hip_stream, except that adaptive Navier-Stokes requests
+ * (fixed_iters = 0) make the host wait once per step for the convergence
+ * flags.  The library keeps one internal plan (tables and workspace) per
+ * size class in use; see pst_batch_cache_bytes.  Errors in a request's
+ * fields or parameters return PST_ERR_INVALID before anything is launched. */
 pst_status solve_batch(const pst_request* reqs, int n, void* hip_stream);
+
+/* Device bytes held by solve_batch's cached internal plans (workspace,
+ * tables, status words), for callers that budget device memory. */
+pst_status pst_batch_cache_bytes(size_t* bytes);
+
+/* Release every cached internal plan of solve_batch (waits for their
+ * streams); the next call recreates what it needs. */
+pst_status pst_batch_cache_release(void);
 
 /* ------------------------------------------------------------- utilities -- */
 

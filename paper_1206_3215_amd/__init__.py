@@ -10,4 +10,4 @@ Nothing is imported eagerly here, so that ``inputs`` can be used without the
 HIP library being present.
 """
 
-__all__ = ["inputs", "binding", "solvers", "serve"]
+__all__ = ["inputs", "binding", "serve"]

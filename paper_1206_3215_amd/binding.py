@@ -72,6 +72,8 @@ _SIGS = {
     "conserved_quantities": [_vp, C.c_int, _vp, _vp, _vp, C.POINTER(C.c_double)],
     "pst_sync_status": [_vp, C.POINTER(C.c_int)],
     "solve_batch": [C.POINTER(Request), C.c_int, _vp],
+    "pst_batch_cache_bytes": [C.POINTER(C.c_size_t)],
+    "pst_batch_cache_release": [],
     "pst_autotune": [_vp, C.c_int, C.POINTER(C.c_int)],
     "pst_set_column_variant": [_vp, C.c_int],
     "pst_column_variant_info": [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
@@ -107,6 +109,20 @@ def _ptr(t) -> int | None:
     if not t.is_contiguous():
         raise ValueError("field must be contiguous")
     return t.data_ptr()
+
+
+def _check(t, name: str, dtype, numel: int | None = None, min_numel: int | None = None) -> None:
+    """Validate a tensor before its pointer crosses the boundary: the kernels
+    trust the dtype and size they are given (a wrong one reads or writes out
+    of bounds).  Raises ValueError; checks nothing about the values."""
+    if t is None:
+        raise ValueError(f"{name} is required")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name}: {t.numel()} elements, expected {numel}")
+    if min_numel is not None and t.numel() < min_numel:
+        raise ValueError(f"{name}: {t.numel()} elements, expected at least {min_numel}")
 
 
 def domain(d) -> Domain:
@@ -151,30 +167,80 @@ class Plan:
         except Exception:
             pass
 
+    # -- argument checks (sizes and dtypes the kernels rely on) -------------
+    @property
+    def _points(self) -> int:
+        return self.batch * self.ny * self.nx
+
+    @property
+    def _half_points(self) -> int:
+        return self.batch * self.ny * (self.nx // 2 + 1)
+
+    def _need_kind(self, kind: int, who: str) -> None:
+        if self.kind != kind:
+            raise ValueError(f"{who} needs a {'C2C' if kind == PST_C2C else 'R2C'} plan")
+
+    def _complex_field(self, t, name: str) -> None:
+        _check(t, name, self.complex_dtype, self._points)
+
+    def _real_field(self, t, name: str) -> None:
+        _check(t, name, self.real_dtype, self._points)
+
     # -- entry points -----------------------------------------------------
     def fft2d_exec(self, inp, out, sign: int) -> None:
+        if self.kind == PST_C2C:
+            self._complex_field(inp, "in")
+            self._complex_field(out, "out")
+        elif sign == -1:
+            self._real_field(inp, "in")
+            _check(out, "out", self.complex_dtype, self._half_points)
+        else:
+            _check(inp, "in", self.complex_dtype, self._half_points)
+            self._real_field(out, "out")
         check(lib.fft2d_exec(self.handle, _ptr(inp), _ptr(out), sign), "fft2d_exec")
 
     def nls_step(self, psi, d, dt: float, g: float, nsteps: int) -> None:
+        self._need_kind(PST_C2C, "nls_step")
+        self._complex_field(psi, "psi")
         p = NlsParams(domain(d), dt, g)
         check(lib.nls_step(self.handle, _ptr(psi), C.byref(p), nsteps), "nls_step")
 
     def sg_start(self, u0, v0, u_prev, u_curr, d, dt: float) -> None:
+        self._need_kind(PST_R2C, "sg_start")
+        for t, name in ((u0, "u0"), (v0, "v0"), (u_prev, "u_prev"), (u_curr, "u_curr")):
+            self._real_field(t, name)
         p = SgParams(domain(d), dt)
         check(lib.sg_start(self.handle, _ptr(u0), _ptr(v0), _ptr(u_prev), _ptr(u_curr), C.byref(p)),
               "sg_start")
 
     def sg_step(self, u_prev, u_curr, d, dt: float, nsteps: int) -> None:
+        self._need_kind(PST_R2C, "sg_step")
+        self._real_field(u_prev, "u_prev")
+        self._real_field(u_curr, "u_curr")
         p = SgParams(domain(d), dt)
         check(lib.sg_step(self.handle, _ptr(u_prev), _ptr(u_curr), C.byref(p), nsteps), "sg_step")
 
     def ns_step(self, omega, d, dt: float, nu: float, nsteps: int, tol: float = 1e-10,
                 max_iter: int = 50, fixed_iters: int = 0, dev_iters=None) -> None:
+        import torch
+        self._need_kind(PST_R2C, "ns_step")
+        self._real_field(omega, "omega")
+        if dev_iters is not None:
+            _check(dev_iters, "dev_iters", torch.int32, min_numel=max(nsteps, 0) * self.batch)
         p = NsParams(domain(d), dt, nu, tol, max_iter, fixed_iters)
         check(lib.ns_step(self.handle, _ptr(omega), C.byref(p), nsteps, _ptr(dev_iters)), "ns_step")
 
     def conserved_quantities(self, eq: str, f0, f1=None, d=None, dt: float = 0.0, g: float = 1.0,
                              nu: float = 0.0) -> np.ndarray:
+        if eq not in EQ:
+            raise ValueError(f"unknown equation {eq!r}")
+        self._need_kind(PST_C2C if eq == "nls" else PST_R2C, f"conserved_quantities({eq})")
+        if eq == "nls":
+            self._complex_field(f0, "f0")
+        else:
+            self._real_field(f0, "f0")
+            if eq == "sg":
+                self._real_field(f1, "f1")
         out = np.zeros(4 * self.batch, dtype=np.float64)
         if eq == "nls":
             p = NlsParams(domain(d), dt, g)
@@ -247,13 +313,28 @@ def solve_batch(requests, stream=None) -> None:
     import torch
     arr = (Request * len(requests))()
     keep = []
+    ptypes = {"nls": NlsParams, "sg": SgParams, "ns": NsParams}
     for i, r in enumerate(requests):
+        eq = r["eq"]
+        if eq not in EQ:
+            raise ValueError(f"request {i}: unknown equation {eq!r}")
         f0 = r["f0"]
+        if f0 is None or f0.dim() < 2 or f0.numel() != f0.shape[-1] * f0.shape[-2]:
+            raise ValueError(f"request {i}: f0 must hold one ny x nx field")
+        allowed = (torch.complex64, torch.complex128) if eq == "nls" else (torch.float32, torch.float64)
+        if f0.dtype not in allowed:
+            raise ValueError(f"request {i}: f0 dtype {f0.dtype} does not suit equation {eq}")
+        if eq == "sg":
+            _check(r.get("f1"), f"request {i}: f1", f0.dtype, f0.numel())
+        if r.get("dev_status") is not None:
+            _check(r["dev_status"], f"request {i}: dev_status", torch.int32, min_numel=1)
+        pr = r["params"]
+        if not isinstance(pr, ptypes[eq]):
+            raise ValueError(f"request {i}: params must be {ptypes[eq].__name__} for equation {eq}")
         prec = PST_FP64 if f0.dtype in (torch.float64, torch.complex128) else PST_FP32
         ny, nx = f0.shape[-2:]
-        pr = r["params"]
         keep.append(pr)
-        arr[i].eq = EQ[r["eq"]]
+        arr[i].eq = EQ[eq]
         arr[i].nx, arr[i].ny, arr[i].prec, arr[i].nsteps = nx, ny, prec, int(r["nsteps"])
         arr[i].params = C.cast(C.pointer(pr), C.c_void_p)
         arr[i].f0 = _ptr(f0)
@@ -261,6 +342,18 @@ def solve_batch(requests, stream=None) -> None:
         arr[i].dev_status = _ptr(r.get("dev_status"))
     st = stream if stream is not None else torch.cuda.current_stream()
     check(lib.solve_batch(arr, len(requests), _vp(st.cuda_stream)), "solve_batch")
+
+
+def batch_cache_bytes() -> int:
+    """Device bytes held by solve_batch's cached internal plans."""
+    n = C.c_size_t()
+    check(lib.pst_batch_cache_bytes(C.byref(n)), "pst_batch_cache_bytes")
+    return int(n.value)
+
+
+def batch_cache_release() -> None:
+    """Free solve_batch's cached internal plans (waits for their streams)."""
+    check(lib.pst_batch_cache_release(), "pst_batch_cache_release")
 
 
 def version() -> str:

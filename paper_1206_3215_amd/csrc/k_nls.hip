@@ -41,7 +41,7 @@ struct PairGeom {
 
 template <typename T, int N, int MODE, int VPT, bool SPLIT, bool UNI>
 __global__ __launch_bounds__((PairGeom<T, N, VPT, SPLIT>::THREADS)) void k_nls_row(
-    FieldRef psi, int npairs, int lny, T phase_coef, T scale, const cpx<T>* __restrict__ tw) {
+    FieldRef psi, int npairs, int lny, T phase_coef, T scale, const cpx<T>* __restrict__ tw, StatusRef st) {
   using G = PairGeom<T, N, VPT, SPLIT>;
   extern __shared__ char smem[];
   const int l = threadIdx.x & 1, q = threadIdx.x >> 1;
@@ -78,6 +78,15 @@ __global__ __launch_bounds__((PairGeom<T, N, VPT, SPLIT>::THREADS)) void k_nls_r
   const unsigned i0 = in_plain ? plain0 : inter0, o0 = out_plain ? plain0 : inter0;
   const unsigned ids = in_plain ? plain_ds : inter_ds, ods = out_plain ? plain_ds : inter_ds;
   constexpr unsigned sz = sizeof(cpx<T>);
+  // the exit pass reports a field holding a non-finite value
+  auto check = [&](int f, bool uniform) {
+    if constexpr (MODE == 2) {
+      bool bad = false;
+#pragma unroll
+      for (int s = 0; s < G::R; ++s) bad = bad || !finite_c(v[s]);
+      latch_nonfinite(bad && valid, st, f, uniform);
+    }
+  };
   if constexpr (UNI) {
     const int f = __builtin_amdgcn_readfirstlane((int)(2 * blockIdx.x * G::P) >> lny);
     const FieldBuf fb(psi.at(f), (unsigned)((size_t)ny * N * sz));
@@ -88,8 +97,10 @@ __global__ __launch_bounds__((PairGeom<T, N, VPT, SPLIT>::THREADS)) void k_nls_r
 #pragma unroll
       for (int s = 0; s < G::R; ++s) fb.st(o0 * sz, s * ods * sz, v[s]);
     }
+    check(f, true);
   } else {
-    gptr<cpx<T>> g = field<cpx<T>>(psi, (2 * pc) >> lny);
+    const int f = (2 * pc) >> lny;
+    gptr<cpx<T>> g = field<cpx<T>>(psi, f);
 #pragma unroll
     for (int s = 0; s < G::R; ++s) v[s] = gload(g + (i0 + s * ids));
     body();
@@ -97,6 +108,8 @@ __global__ __launch_bounds__((PairGeom<T, N, VPT, SPLIT>::THREADS)) void k_nls_r
 #pragma unroll
       for (int s = 0; s < G::R; ++s) gstore(g + (o0 + s * ods), v[s]);
     }
+    // a wave spans 64/TL rows of whole pairs, all in one field when ny >= 64/TL
+    check(f, ny * G::TL >= 64);
   }
 }
 
@@ -198,18 +211,19 @@ struct NlsRowCfg {
 };
 
 template <typename T, int N, int MODE, bool UNI>
-static void launch_row(int npairs, int ny, FieldRef psi, double pc, double scale, const void* tw, hipStream_t s) {
+static void launch_row(int npairs, int ny, FieldRef psi, double pc, double scale, const void* tw, hipStream_t s,
+                       StatusRef st) {
   using C = NlsRowCfg<T, N>;
   using G = PairGeom<T, N, C::VPT, C::SPLIT>;
   auto* k = &k_nls_row<T, N, MODE, C::VPT, C::SPLIT, UNI>;
   allow_lds(k, G::LDS_BYTES);
   hipLaunchKernelGGL(k, dim3((npairs + G::P - 1) / G::P), dim3(G::THREADS), G::LDS_BYTES, s, psi, npairs,
-                     ilog2c(ny), (T)pc, (T)scale, (const cpx<T>*)tw);
+                     ilog2c(ny), (T)pc, (T)scale, (const cpx<T>*)tw, st);
 }
 
 template <typename T>
 static hipError_t row(int nx, int nlines, int ny, FieldRef psi, int mode, double pc, double scale,
-                      const void* tw, hipStream_t s) {
+                      const void* tw, hipStream_t s, StatusRef st) {
   if (ny % 2 != 0 || nlines % 2 != 0) return hipErrorInvalidValue;
   bool ok = dispatch_n(nx, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
@@ -227,9 +241,9 @@ static hipError_t row(int nx, int nlines, int ny, FieldRef psi, int mode, double
         hipLaunchKernelGGL(k, dim3(nlines), dim3(N / C::VPT), lds, s, psi, ilog2c(ny), (T)pc, (T)scale,
                            (const cpx<T>*)tw);
       } else if (uni) {
-        launch_row<T, N, MODE, true>(nlines / 2, ny, psi, pc, scale, tw, s);
+        launch_row<T, N, MODE, true>(nlines / 2, ny, psi, pc, scale, tw, s, st);
       } else {
-        launch_row<T, N, MODE, false>(nlines / 2, ny, psi, pc, scale, tw, s);
+        launch_row<T, N, MODE, false>(nlines / 2, ny, psi, pc, scale, tw, s, st);
       }
     };
     if (mode == 0) go(IntC<0>{});
@@ -240,9 +254,9 @@ static hipError_t row(int nx, int nlines, int ny, FieldRef psi, int mode, double
 }
 
 hipError_t nls_row(Prec p, int nx, int nlines, int ny, FieldRef psi, int mode, double phase_coef, double scale,
-                   const void* tw, hipStream_t s) {
-  return p == P32 ? row<float>(nx, nlines, ny, psi, mode, phase_coef, scale, tw, s)
-                  : row<double>(nx, nlines, ny, psi, mode, phase_coef, scale, tw, s);
+                   const void* tw, hipStream_t s, StatusRef st) {
+  return p == P32 ? row<float>(nx, nlines, ny, psi, mode, phase_coef, scale, tw, s, st)
+                  : row<double>(nx, nlines, ny, psi, mode, phase_coef, scale, tw, s, st);
 }
 
 template <typename T>

@@ -358,6 +358,7 @@ __global__ __launch_bounds__(256) void k_ns_finish(int ncols, const double* part
     if (!isfinite(res)) {
       fin = true;
       atomicOr(status, (int)ST_NONFINITE);
+      if (fstat != nullptr && fstat[f] != nullptr) atomicOr(fstat[f], (int)ST_NONFINITE);
     }
     done[f] = fin ? 1 : 0;
     if (iters_out) iters_out[f] = it;

@@ -32,7 +32,7 @@ __device__ __forceinline__ double sin_of(double x) { return sin(x); }
 template <typename T, int N, int MODE>
 __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_row(
     const cpx<T>* W, FieldRef u_old_f, FieldRef d_old_f, T alpha, FieldRef u_out_f, FieldRef d_out_f,
-    FieldRef prev_out_f, cpx<T>* U, cpx<T>* S, int nlines, int lny, const cpx<T>* __restrict__ tw) {
+    FieldRef prev_out_f, cpx<T>* U, cpx<T>* S, int nlines, int lny, const cpx<T>* __restrict__ tw, StatusRef st) {
   using G = RowGeom<T, N>;
   constexpr int H = N / 2 + 1;
   extern __shared__ char smem[];
@@ -88,6 +88,14 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_row(
       }
       if (va) u_out[ra + e] = u[s].re;
       if (vb) u_out[rb + e] = u[s].im;
+    }
+    if constexpr (MODE == SG_FINAL) {
+      // the last pass of a call reports a field holding a non-finite value
+      bool bad = false;
+#pragma unroll
+      for (int s = 0; s < G::R; ++s) bad = bad || (va && !isfinite(u[s].re)) || (vb && !isfinite(u[s].im));
+      // a wave spans 128/TL rows of whole pairs, all in one field when ny >= 128/TL
+      latch_nonfinite(bad, st, f, G::TL >= 64 || (1 << lny) * G::TL >= 128);
     }
   }
   if constexpr (MODE == SG_STEP) {
@@ -285,7 +293,7 @@ __global__ __launch_bounds__(256) void k_sg_h_finish(int npairs, int ncols, cons
 template <typename T>
 static hipError_t row(int mode, int nx, int nlines, int ny, const void* W, FieldRef u_old, FieldRef d_old,
                       double alpha, FieldRef u_out, FieldRef d_out, FieldRef prev_out, void* U, void* S,
-                      const void* tw, hipStream_t s) {
+                      const void* tw, hipStream_t s, StatusRef st) {
   if (nlines % 2 != 0) return hipErrorInvalidValue;  // the kernels take rows in pairs
   bool ok = dispatch_n(nx, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
@@ -295,7 +303,7 @@ static hipError_t row(int mode, int nx, int nlines, int ny, const void* W, Field
       allow_lds(kern, G::LDS_BYTES);
       hipLaunchKernelGGL(kern, dim3(grid), dim3(G::THREADS), G::LDS_BYTES, s, (const cpx<T>*)W, u_old, d_old,
                          (T)alpha, u_out, d_out, prev_out, (cpx<T>*)U, (cpx<T>*)S, nlines, ilog2c(ny),
-                         (const cpx<T>*)tw);
+                         (const cpx<T>*)tw, st);
     };
     if (mode == SG_ENTRY) go(k_sg_row<T, N, SG_ENTRY>);
     else if (mode == SG_STEP) go(k_sg_row<T, N, SG_STEP>);
@@ -306,9 +314,10 @@ static hipError_t row(int mode, int nx, int nlines, int ny, const void* W, Field
 
 hipError_t sg_row(Prec p, int mode, int nx, int nlines, int ny, const void* W, FieldRef u_old, FieldRef d_old,
                   double alpha, FieldRef u_out, FieldRef d_out, FieldRef prev_out, void* U, void* S,
-                  const void* tw, hipStream_t s) {
-  return p == P32 ? row<float>(mode, nx, nlines, ny, W, u_old, d_old, alpha, u_out, d_out, prev_out, U, S, tw, s)
-                  : row<double>(mode, nx, nlines, ny, W, u_old, d_old, alpha, u_out, d_out, prev_out, U, S, tw, s);
+                  const void* tw, hipStream_t s, StatusRef st) {
+  return p == P32 ? row<float>(mode, nx, nlines, ny, W, u_old, d_old, alpha, u_out, d_out, prev_out, U, S, tw, s, st)
+                  : row<double>(mode, nx, nlines, ny, W, u_old, d_old, alpha, u_out, d_out, prev_out, U, S, tw, s,
+                                st);
 }
 
 template <typename T>

@@ -337,6 +337,25 @@ __device__ __forceinline__ double line_sum(double* red, int line, int t, int n, 
   return out;
 }
 
+template <typename T>
+__device__ __forceinline__ bool finite_c(cpx<T> v) {
+  return isfinite(v.re) && isfinite(v.im);
+}
+
+// Latch ST_NONFINITE for field f when this thread saw a non-finite value.
+// Only the first such lane of a wave writes when the whole wave works on
+// field f (wave_uniform), so a field flooded with NaN costs one atomic per
+// wave; otherwise every such lane writes its own field's word.
+__device__ __forceinline__ void latch_nonfinite(bool bad, const StatusRef& st, int f, bool wave_uniform) {
+  if (!bad) return;
+  if (wave_uniform) {
+    const unsigned long long m = __ballot(1);  // lanes with bad set (the others returned)
+    if ((int)(__lane_id()) != __ffsll((long long)m) - 1) return;
+  }
+  if (st.plan != nullptr) atomicOr(st.plan, (int)ST_NONFINITE);
+  if (st.field != nullptr && st.field[f] != nullptr) atomicOr(st.field[f], (int)ST_NONFINITE);
+}
+
 // Kernels whose dynamic LDS exceeds 64 KiB must opt in once (gfx950 has
 // 160 KiB per workgroup).
 template <class K>

@@ -30,6 +30,14 @@ inline FieldRef contiguous(const void* p, size_t field_bytes) {
 // Status bits latched by kernels into a plan's device status word.
 enum : int { ST_NONFINITE = 1, ST_NOT_CONVERGED = 2 };
 
+// Where a kernel latches a status bit: the plan-wide word and, for batched
+// requests, a per-field word reached through a device pointer table (either
+// may be NULL; so may a table entry).
+struct StatusRef {
+  int* plan = nullptr;
+  int* const* field = nullptr;
+};
+
 // Column-pass tiles compiled for length n: the widest (W columns per block,
 // bounded by the block size and the LDS footprint) and its half.
 // Column tile variant `var` for lines of length n: columns per block,
@@ -60,8 +68,10 @@ hipError_t fft_row_c2r(Prec p, int n, int nlines, int ny, const void* in, FieldR
 // ----------------------------------------------------------------- NLS ---
 // mode 0: H = nx * FFT_x(psi); 1: H <- FFT_x(e^{-i c |iFFT_x H|^2} iFFT_x H);
 // 2: psi = iFFT_x(H) / nx.  phase_coef = g dt / nx^2, scale as stated.
+// Mode 2 latches ST_NONFINITE into st for a field whose result holds a
+// non-finite value.
 hipError_t nls_row(Prec p, int nx, int nlines, int ny, FieldRef psi, int mode, double phase_coef,
-                   double scale, const void* tw, hipStream_t s);
+                   double scale, const void* tw, hipStream_t s, StatusRef st = StatusRef());
 // Column: FFT_y, multiply by (1 + ex[mx]) (1 + ey[my]) / (nx ny), iFFT_y (in place).
 hipError_t nls_col(Prec p, int ny, int nx, int nfields, FieldRef psi, const void* tw,
                    const void* ex, const void* ey, int W, hipStream_t s);
@@ -86,11 +96,12 @@ hipError_t nls_cq_finish(int nfields, int ny, int nx, const double* row_part,
 //                   not NULL, d_out = u_old - d_old.
 //   mode 1 (step):  d_out = d_old + C2R_x(W); u_out = u_old + d_out; U, S.
 //   mode 2 (final): d = alpha d_old + C2R_x(W); u_out = u_old + d;
-//                   prev_out = u_old.
+//                   prev_out = u_old; ST_NONFINITE latched into st for a
+//                   field whose u_out holds a non-finite value.
 // Each element is read before it is written, so outputs may alias inputs.
 hipError_t sg_row(Prec p, int mode, int nx, int nlines, int ny, const void* W, FieldRef u_old, FieldRef d_old,
                   double alpha, FieldRef u_out, FieldRef d_out, FieldRef prev_out, void* U, void* S,
-                  const void* tw, hipStream_t s);
+                  const void* tw, hipStream_t s, StatusRef st = StatusRef());
 // Column pass: W = iFFT_y(c1m FFT_y(U) - c2 FFT_y(S)) with a = |k|^2 dt2q,
 // c1m = -2 cnum a/(1+a) sc, c2 = c2num/(1+a) sc.
 hipError_t sg_col(Prec p, int ny, int nx, int nfields, const void* U, const void* S, void* W, const void* tw,

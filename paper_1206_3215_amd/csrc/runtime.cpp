@@ -135,7 +135,7 @@ pst_status check_domain(const pst_domain& d) {
 
 pst_status check_field(const void* p, const char* name) {
   if (p == nullptr) return fail(PST_ERR_INVALID, "%s is NULL", name);
-  if (reinterpret_cast<uintptr_t>(p) % 16 != 0) return fail(PST_ERR_INVALID, "%s is not 16-byte aligned", name);
+  if (reinterpret_cast<uintptr_t>(p) % 256 != 0) return fail(PST_ERR_INVALID, "%s is not 256-byte aligned", name);
   return PST_OK;
 }
 

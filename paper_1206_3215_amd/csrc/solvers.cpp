@@ -18,6 +18,12 @@
 
 using namespace pst;
 
+#define TRY(expr)                       \
+  do {                                  \
+    pst_status st_ = (expr);            \
+    if (st_ != PST_OK) return st_;      \
+  } while (0)
+
 namespace {
 
 // exp(-i k^2 tau) - 1 = (cos - 1, -sin) for the n wavenumbers of a period,
@@ -36,6 +42,9 @@ std::vector<std::complex<double>> propagator_m1(int n, double length, double tau
 pst_status nls_tables(Plan* pl, const pst_nls_params* p) {
   NlsTables& t = pl->nls;
   if (t.valid && t.dt == p->dt && t.lx == p->d.lx && t.ly == p->d.ly) return PST_OK;
+  // the tables are rewritten in place: passes still queued with the old ones
+  // (this plan's stream) must have finished before the synchronous upload
+  if (t.valid) TRY(hip_check(hipStreamSynchronize(pl->stream), "hipStreamSynchronize(tables)"));
   pst_status st = upload_complex(pl, propagator_m1(pl->nx, p->d.lx, 0.5 * p->dt), &t.ex_half, false, 1.0);
   if (st == PST_OK) st = upload_complex(pl, propagator_m1(pl->nx, p->d.lx, p->dt), &t.ex_full, false, 1.0);
   if (st == PST_OK) st = upload_complex(pl, propagator_m1(pl->ny, p->d.ly, 0.5 * p->dt), &t.ey_half, false, 1.0);
@@ -55,12 +64,6 @@ pst_status need_kind(Plan* pl, pst_kind k, const char* who) {
   return PST_OK;
 }
 
-#define TRY(expr)                       \
-  do {                                  \
-    pst_status st_ = (expr);            \
-    if (st_ != PST_OK) return st_;      \
-  } while (0)
-
 }  // namespace
 
 extern "C" {
@@ -75,8 +78,11 @@ static pst_status nls_check(Plan* pl, const pst_nls_params* p, int nsteps) {
   return PST_OK;
 }
 
-// nsteps Strang steps of the pl->batch fields addressed by psi.
-static pst_status nls_run(Plan* pl, FieldRef psi, const pst_nls_params* p, int nsteps) {
+// nsteps Strang steps of the pl->batch fields addressed by psi; fstat (a
+// device table of per-field status words, may be NULL) receives
+// ST_NONFINITE for a field whose result is not finite.
+static pst_status nls_run(Plan* pl, FieldRef psi, const pst_nls_params* p, int nsteps,
+                          int* const* fstat = nullptr) {
   if (nsteps == 0) return PST_OK;
   TRY(nls_tables(pl, p));
   const int nx = pl->nx, ny = pl->ny, B = pl->batch, W = pl->colvar;
@@ -104,7 +110,10 @@ static pst_status nls_run(Plan* pl, FieldRef psi, const pst_nls_params* p, int n
   }
   TRY(row(1, pc, 1.0));
   TRY(col(t.ex_half, t.ey_half));
-  return row(2, 0.0, 1.0 / nx);
+  StatusRef sr;
+  sr.plan = pl->dstatus;
+  sr.field = fstat;
+  return hip_check(nls_row(pl->P, nx, lines, ny, psi, 2, 0.0, 1.0 / nx, pl->tw_x, s, sr), "nls exit row");
 }
 
 pst_status nls_step(pst_plan pl, void* psi, const pst_nls_params* p, int nsteps) {
@@ -213,8 +222,9 @@ pst_status sg_start(pst_plan pl, const void* u0, const void* v0, void* u_prev, v
                    "sg start row");
 }
 
-// nsteps of the pl->batch field pairs (u_prev, u_curr).
-static pst_status sg_run(Plan* pl, FieldRef u_prev, FieldRef u_curr, const pst_sg_params* p, int nsteps) {
+// nsteps of the pl->batch field pairs (u_prev, u_curr); fstat as in nls_run.
+static pst_status sg_run(Plan* pl, FieldRef u_prev, FieldRef u_curr, const pst_sg_params* p, int nsteps,
+                         int* const* fstat = nullptr) {
   if (nsteps == 0) return PST_OK;
   const int nx = pl->nx, ny = pl->ny, B = pl->batch, lines = B * ny;
   void* U = ws_at(pl, pl->off_spec);
@@ -245,8 +255,11 @@ static pst_status sg_run(Plan* pl, FieldRef u_prev, FieldRef u_curr, const pst_s
     TRY(col());
   }
   // last step: u_curr <- u^N, u_prev <- u^{N-1} (the level it replaces)
+  StatusRef sr;
+  sr.plan = pl->dstatus;
+  sr.field = fstat;
   return hip_check(sg_row(pl->P, 2, nx, lines, ny, W, u_curr, u_prev, 1.0, u_curr, none, u_prev, nullptr, nullptr,
-                          pl->tw_x, s),
+                          pl->tw_x, s, sr),
                    "sg final row");
 }
 
@@ -539,71 +552,98 @@ extern "C" pst_status pst_autotune(pst_plan pl, pst_eq eq, int* chosen) {
 
 // ------------------------------------------------------------ batching ---
 // solve_batch groups requests that share (equation, nx, ny, precision,
-// parameters).  Each group runs on an internal plan whose capacity is the
-// next power of two of the group size; the callers' fields are reached
-// through device pointer tables, so nothing is gathered or copied.  Groups
-// are forked onto library-owned streams (default priority) and joined back
-// on the caller's stream, so size classes overlap on the device.  Requests
-// of one group with different step counts advance in chunks of the smallest
-// remaining count; a chunk's launch sequence is captured once into a
-// hipGraph and replayed when the same (plan, fields, chunk) comes back.
+// parameters).  Each group runs on an internal plan of its size class whose
+// capacity is the next power of two of the group size; the callers' fields
+// are reached through device pointer tables, so nothing is gathered or
+// copied.  Groups are forked onto at most kSideStreams library-owned streams
+// (default priority) and joined back on the caller's stream, so size classes
+// overlap on the device.  Requests of one group with different step counts
+// advance in chunks of the smallest remaining count; a chunk's launch
+// sequence is captured into a hipGraph and replayed when the same (fields,
+// chunk, parameters) comes back.
 namespace {
 
-struct GroupKey {
-  int eq, nx, ny, prec, cap;
-  hipStream_t stream;
-  bool operator<(const GroupKey& o) const {
-    return std::tie(eq, nx, ny, prec, cap, stream) < std::tie(o.eq, o.nx, o.ny, o.prec, o.cap, o.stream);
+// Plans are cached per size class and slot: slot s serves the s-th group of
+// that class in one call (groups of a class differ only by parameters), so
+// the cache holds one plan per class unless calls mix parameter sets.
+struct ClassKey {
+  int eq, nx, ny, prec, slot;
+  bool operator<(const ClassKey& o) const {
+    return std::tie(eq, nx, ny, prec, slot) < std::tie(o.eq, o.nx, o.ny, o.prec, o.slot);
   }
 };
 
 struct BatchPlan {
   Plan* pl = nullptr;
-  void** dtab = nullptr;  // device: cap x {f0, f1, status slot}
-  int* dfst = nullptr;    // device: per-field status (NS)
-  // chunk schedules (fields, steps) seen once, and the graphs of those seen
-  // again: a schedule is captured on its second occurrence and replayed
-  // from the third on, so one-off schedules (a serving loop's changing mix)
-  // never pay for a capture
+  void** dtab = nullptr;      // device: cap x {f0, f1, per-field status pointer, caller status pointer}
+  int* dfst = nullptr;        // device: per-field status bits
+  size_t tab_bytes = 0;
+  hipEvent_t last = nullptr;  // recorded on the plan's stream after its last use
+  bool used = false;          // last has been recorded
+  // chunk schedules seen once, and the graphs of those seen again: a
+  // schedule is captured on its second occurrence and replayed from the
+  // third on, so one-off schedules (a serving loop's changing mix) never pay
+  // for a capture
   std::map<std::vector<uintptr_t>, int> seen;
   std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
 };
 constexpr size_t kMaxGraphs = 64, kMaxSeen = 4096;
+// One side stream per hardware queue a process gets by default; further
+// groups share them round robin (and run one after another on each).
+constexpr int kSideStreams = 4;
 
 std::mutex g_batch_mu;
-std::map<GroupKey, BatchPlan> g_batch_plans;
+std::map<ClassKey, BatchPlan> g_batch_plans;
 std::vector<hipStream_t> g_side_streams;
 
 size_t params_size(int eq) {
   return eq == PST_NLS ? sizeof(pst_nls_params) : eq == PST_SG ? sizeof(pst_sg_params) : sizeof(pst_ns_params);
 }
 
-// One cached plan per (equation, size, precision, stream); a larger group
-// replaces it with a plan of the next power-of-two capacity, so the cache
-// holds at most one workspace per size class.
-pst_status batch_plan(const pst_request& r, int cap, hipStream_t s, BatchPlan** out) {
-  GroupKey k{(int)r.eq, r.nx, r.ny, (int)r.prec, 0, s};
+void destroy_batch_plan(BatchPlan& bp) {
+  for (auto& g : bp.graphs) hipGraphExecDestroy(g.second);
+  bp.graphs.clear();
+  if (bp.pl != nullptr) fft2d_destroy(bp.pl);  // synchronises the stream it last ran on
+  if (bp.last != nullptr) hipEventDestroy(bp.last);
+  bp.pl = nullptr;
+  bp.last = nullptr;
+}
+
+// The cached plan of (class, slot) with room for cap fields, on stream s:
+// s first waits for the plan's previous use (possibly on another stream),
+// which still owns the workspace until then.
+pst_status batch_plan(const pst_request& r, int slot, int cap, hipStream_t s, BatchPlan** out) {
+  ClassKey k{(int)r.eq, r.nx, r.ny, (int)r.prec, slot};
   auto it = g_batch_plans.find(k);
-  if (it != g_batch_plans.end()) {
-    if (it->second.pl->batch >= cap) {
-      *out = &it->second;
-      return PST_OK;
-    }
-    for (auto& g : it->second.graphs) hipGraphExecDestroy(g.second);
-    fft2d_destroy(it->second.pl);
+  if (it != g_batch_plans.end() && it->second.pl->batch < cap) {
+    destroy_batch_plan(it->second);
     g_batch_plans.erase(it);
+    it = g_batch_plans.end();
   }
-  BatchPlan bp;
-  TRY(fft2d_plan(r.nx, r.ny, r.eq == PST_NLS ? PST_C2C : PST_R2C, r.prec, cap, s, &bp.pl));
-  TRY(ensure_workspace(bp.pl));
-  TRY(pst_autotune(bp.pl, r.eq, nullptr));
-  void* p = nullptr;
-  TRY(hip_check(hipMalloc(&p, (size_t)cap * (4 * sizeof(void*) + sizeof(int)) + 256), "hipMalloc(tables)"));
-  bp.pl->owned.push_back(p);
-  bp.dtab = static_cast<void**>(p);
-  bp.dfst = reinterpret_cast<int*>(static_cast<char*>(p) + (size_t)cap * 4 * sizeof(void*));
-  auto res = g_batch_plans.emplace(k, bp);
-  *out = &res.first->second;
+  if (it == g_batch_plans.end()) {
+    BatchPlan bp;
+    pst_status st = fft2d_plan(r.nx, r.ny, r.eq == PST_NLS ? PST_C2C : PST_R2C, r.prec, cap, s, &bp.pl);
+    if (st == PST_OK) st = ensure_workspace(bp.pl);
+    if (st == PST_OK) st = pst_autotune(bp.pl, r.eq, nullptr);
+    void* p = nullptr;
+    bp.tab_bytes = (size_t)cap * (4 * sizeof(void*) + sizeof(int)) + 256;
+    if (st == PST_OK) st = hip_check(hipMalloc(&p, bp.tab_bytes), "hipMalloc(tables)");
+    if (st == PST_OK) {
+      bp.pl->owned.push_back(p);
+      bp.dtab = static_cast<void**>(p);
+      bp.dfst = reinterpret_cast<int*>(static_cast<char*>(p) + (size_t)cap * 4 * sizeof(void*));
+      st = hip_check(hipEventCreateWithFlags(&bp.last, hipEventDisableTiming), "hipEventCreate");
+    }
+    if (st != PST_OK) {
+      destroy_batch_plan(bp);
+      return st;
+    }
+    it = g_batch_plans.emplace(k, bp).first;
+  }
+  BatchPlan& bp = it->second;
+  if (bp.used && bp.pl->stream != s) TRY(hip_check(hipStreamWaitEvent(s, bp.last, 0), "hipStreamWaitEvent"));
+  bp.pl->stream = s;
+  *out = &bp;
   return PST_OK;
 }
 
@@ -613,15 +653,29 @@ pst_status check_request(const pst_request& r, int i) {
     return fail(PST_ERR_INVALID, "request %d: sizes must be powers of two in [4, 8192]", i);
   if (r.prec != PST_FP32 && r.prec != PST_FP64) return fail(PST_ERR_INVALID, "request %d: unknown precision", i);
   if (r.nsteps < 0) return fail(PST_ERR_INVALID, "request %d: nsteps < 0", i);
-  if (r.params == nullptr || r.f0 == nullptr || (r.eq == PST_SG && r.f1 == nullptr))
-    return fail(PST_ERR_INVALID, "request %d: NULL params or field", i);
+  if (r.params == nullptr) return fail(PST_ERR_INVALID, "request %d: params is NULL", i);
+  pst_status st = check_field(r.f0, "f0");
+  if (st == PST_OK && r.eq == PST_SG) st = check_field(r.f1, "f1");
+  if (st != PST_OK) return fail(st, "request %d: %s", i, pst_last_error());
   if (r.eq == PST_SG && r.f0 == r.f1) return fail(PST_ERR_INVALID, "request %d: u_prev and u_curr must differ", i);
+  if (reinterpret_cast<uintptr_t>(r.dev_status) % alignof(int) != 0)
+    return fail(PST_ERR_INVALID, "request %d: dev_status is not int-aligned", i);
   return PST_OK;
 }
 
+// Per-request status: the group's per-field bits mapped to a pst_status and
+// latched into the caller's word.  A failure already recorded there by an
+// earlier call (PST_ERR_NOT_CONVERGED or PST_ERR_NONFINITE) is kept unless
+// this call found a worse one; anything else is overwritten.  NONFINITE
+// outranks NOT_CONVERGED.
 __global__ void k_scatter_status(const int* fst, int* const* dst, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && dst[i] != nullptr) *dst[i] = (fst[i] & ST_NOT_CONVERGED) ? PST_ERR_NOT_CONVERGED : PST_OK;
+  if (i >= n || dst[i] == nullptr) return;
+  const int b = fst[i];
+  const int now = (b & ST_NONFINITE) ? PST_ERR_NONFINITE : (b & ST_NOT_CONVERGED) ? PST_ERR_NOT_CONVERGED : PST_OK;
+  const int old = *dst[i];
+  const int kept = (old == PST_ERR_NONFINITE || old == PST_ERR_NOT_CONVERGED) ? old : PST_OK;
+  *dst[i] = now > kept ? now : kept;
 }
 
 }  // namespace
@@ -645,8 +699,8 @@ static pst_status run_chunk(BatchPlan& bp, int eq, const void* params, int nf, i
   // tables are uploaded before any capture (a synchronous copy may not be captured)
   if (eq == PST_NLS) TRY(nls_tables(pl, static_cast<const pst_nls_params*>(params)));
   auto launch = [&]() -> pst_status {
-    if (eq == PST_NLS) return nls_run(pl, f0, static_cast<const pst_nls_params*>(params), k);
-    if (eq == PST_SG) return sg_run(pl, f0, f1, static_cast<const pst_sg_params*>(params), k);
+    if (eq == PST_NLS) return nls_run(pl, f0, static_cast<const pst_nls_params*>(params), k, fst);
+    if (eq == PST_SG) return sg_run(pl, f0, f1, static_cast<const pst_sg_params*>(params), k, fst);
     return ns_run(pl, f0, static_cast<const pst_ns_params*>(params), k, nullptr, fst);
   };
   auto g = bp.graphs.end();
@@ -689,9 +743,13 @@ extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stre
   for (int i = 0; i < n; ++i) TRY(check_request(reqs[i], i));
   std::lock_guard<std::mutex> lock(g_batch_mu);
   hipStream_t caller = reinterpret_cast<hipStream_t>(hip_stream);
-  // group by (eq, nx, ny, prec, parameter bytes)
+  // group by (eq, nx, ny, prec, parameter bytes); slot = index of the group
+  // among this call's groups of the same size class
   std::vector<std::vector<int>> groups;
+  std::vector<std::vector<unsigned char>> gkeys;
+  std::vector<int> slots;
   std::map<std::vector<unsigned char>, int> gidx;
+  std::map<std::tuple<int, int, int, int>, int> per_class;
   for (int i = 0; i < n; ++i) {
     const pst_request& r = reqs[i];
     std::vector<unsigned char> key(5 * sizeof(int) + params_size(r.eq));
@@ -702,11 +760,14 @@ extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stre
     if (it == gidx.end()) {
       gidx.emplace(key, (int)groups.size());
       groups.push_back({i});
+      gkeys.push_back(key);
+      slots.push_back(per_class[std::make_tuple((int)r.eq, r.nx, r.ny, (int)r.prec)]++);
     } else {
       groups[it->second].push_back(i);
     }
   }
-  while (g_side_streams.size() < groups.size()) {
+  const int nstreams = std::min<int>(kSideStreams, (int)groups.size());
+  while ((int)g_side_streams.size() < nstreams) {
     hipStream_t st;
     TRY(hip_check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate"));
     g_side_streams.push_back(st);
@@ -714,6 +775,9 @@ extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stre
   hipEvent_t fork;
   TRY(hip_check(hipEventCreateWithFlags(&fork, hipEventDisableTiming), "hipEventCreate"));
   TRY(hip_check(hipEventRecord(fork, caller), "hipEventRecord"));
+  pst_status result = PST_OK;
+  for (int i = 0; i < nstreams && result == PST_OK; ++i)
+    result = hip_check(hipStreamWaitEvent(g_side_streams[i], fork, 0), "hipStreamWaitEvent");
   // Prepare every group on this thread (plan cache, autotuning, checks).
   struct Job {
     size_t gi;
@@ -721,16 +785,13 @@ extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stre
     bool adaptive;  // NS with a convergence test: host checks once per step
   };
   std::vector<Job> jobs;
-  pst_status result = PST_OK;
   for (size_t gi = 0; gi < groups.size() && result == PST_OK; ++gi) {
     const pst_request& r0 = reqs[groups[gi][0]];
-    hipStream_t s = g_side_streams[gi];
-    result = hip_check(hipStreamWaitEvent(s, fork, 0), "hipStreamWaitEvent");
-    if (result != PST_OK) break;
+    hipStream_t s = g_side_streams[gi % kSideStreams];
     int cap = 1;
     while (cap < (int)groups[gi].size()) cap <<= 1;
     BatchPlan* bp = nullptr;
-    if ((result = batch_plan(r0, cap, s, &bp)) != PST_OK) break;
+    if ((result = batch_plan(r0, slots[gi], cap, s, &bp)) != PST_OK) break;
     // validate the shared parameters through the single-plan checks
     Plan* pl = bp->pl;
     if (r0.eq == PST_NLS) result = nls_check(pl, static_cast<const pst_nls_params*>(r0.params), 0);
@@ -738,8 +799,10 @@ extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stre
     else result = ns_check(pl, static_cast<const pst_ns_params*>(r0.params), 0);
     const bool adaptive = r0.eq == PST_NS && static_cast<const pst_ns_params*>(r0.params)->fixed_iters <= 0;
     jobs.push_back({gi, bp, adaptive});
+    // per-field status bits start clear for this call
+    if (result == PST_OK)
+      result = hip_check(hipMemsetAsync(bp->dfst, 0, cap * sizeof(int), s), "clear status");
   }
-  std::vector<hipEvent_t> joins(jobs.size(), nullptr);
   // table of a chunk's active requests: f0, f1 and status slots
   auto upload_table = [&](size_t ji, const std::vector<int>& act, std::vector<uintptr_t>* key) -> pst_status {
     const std::vector<int>& g = groups[jobs[ji].gi];
@@ -775,7 +838,6 @@ extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stre
   auto close_group = [&](size_t ji) -> pst_status {
     const std::vector<int>& g = groups[jobs[ji].gi];
     BatchPlan* bp = jobs[ji].bp;
-    const pst_request& r0 = reqs[g[0]];
     hipStream_t s = bp->pl->stream;
     const int cap = bp->pl->batch;
     std::vector<int*> stp(g.size());
@@ -785,7 +847,6 @@ extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stre
       any = any || stp[j] != nullptr;
     }
     if (any) {
-      if (r0.eq != PST_NS) TRY(hip_check(hipMemsetAsync(bp->dfst, 0, cap * sizeof(int), s), "clear status"));
       int** dst = reinterpret_cast<int**>(bp->dtab + 3 * cap);
       TRY(hip_check(hipMemcpyAsync(dst, stp.data(), g.size() * sizeof(int*), hipMemcpyHostToDevice, s),
                     "upload status table"));
@@ -793,10 +854,8 @@ extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stre
                          (int)g.size());
       TRY(hip_check(hipGetLastError(), "status scatter"));
     }
-    hipEvent_t j;
-    TRY(hip_check(hipEventCreateWithFlags(&j, hipEventDisableTiming), "hipEventCreate"));
-    TRY(hip_check(hipEventRecord(j, s), "hipEventRecord"));
-    joins[ji] = j;
+    TRY(hip_check(hipEventRecord(bp->last, s), "hipEventRecord"));
+    bp->used = true;
     return PST_OK;
   };
   // fixed-schedule group: chunk after chunk, each a graph replay once seen
@@ -804,15 +863,22 @@ extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stre
     const std::vector<int>& g = groups[jobs[ji].gi];
     BatchPlan* bp = jobs[ji].bp;
     const pst_request& r0 = reqs[g[0]];
+    const std::vector<unsigned char>& pk = gkeys[jobs[ji].gi];
     std::vector<int> left(g.size()), act;
     for (size_t j = 0; j < g.size(); ++j) left[j] = reqs[g[j]].nsteps;
-    if (r0.eq == PST_NS)
-      TRY(hip_check(hipMemsetAsync(bp->dfst, 0, bp->pl->batch * sizeof(int), bp->pl->stream), "clear status"));
     for (int k; (k = next_chunk(left, &act)) > 0;) {
       std::vector<uintptr_t> key;
       TRY(upload_table(ji, act, &key));
       key.push_back((uintptr_t)k);
       key.push_back((uintptr_t)act.size());
+      // the captured launches carry the parameters (time step, domain,
+      // coefficients) as kernel arguments: a graph is replayed only for the
+      // same parameter bytes
+      for (size_t b = 0; b < pk.size(); b += sizeof(uintptr_t)) {
+        uintptr_t w = 0;
+        memcpy(&w, pk.data() + b, std::min(sizeof(uintptr_t), pk.size() - b));
+        key.push_back(w);
+      }
       TRY(run_chunk(*bp, r0.eq, r0.params, (int)act.size(), k, true, key));
       for (int a : act) left[a] -= k;
     }
@@ -843,8 +909,6 @@ extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stre
     q.left.resize(g.size());
     for (size_t j = 0; j < g.size(); ++j) q.left[j] = reqs[g[j]].nsteps;
     q.cap = jobs[q.ji].bp->pl->batch;
-    result = hip_check(hipMemsetAsync(jobs[q.ji].bp->dfst, 0, q.cap * sizeof(int), jobs[q.ji].bp->pl->stream),
-                       "clear status");
   }
   for (bool busy = true; busy && result == PST_OK;) {
     busy = false;
@@ -885,13 +949,29 @@ extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stre
     }
   }
   for (NsGroup& q : ns) jobs[q.ji].bp->pl->batch = q.cap;  // also after an error
-  for (hipEvent_t j : joins) {
-    if (j == nullptr) continue;
-    hipStreamWaitEvent(caller, j, 0);
-    hipEventDestroy(j);
-  }
+  for (const Job& j : jobs)
+    if (j.bp->used) hipStreamWaitEvent(caller, j.bp->last, 0);
   hipEventDestroy(fork);
   return result;
 }
 
+extern "C" pst_status pst_batch_cache_bytes(size_t* bytes) {
+  if (bytes == nullptr) return fail(PST_ERR_INVALID, "bytes is NULL");
+  std::lock_guard<std::mutex> lock(g_batch_mu);
+  size_t tot = 0;
+  for (auto& e : g_batch_plans) {
+    const Plan* pl = e.second.pl;
+    tot += pl->ws_need + e.second.tab_bytes + 256 + (size_t)pl->batch * 8 * sizeof(double);
+    tot += (size_t)(pl->nx + pl->ny) * pl->csize;  // twiddles
+    if (pl->kind == PST_C2C) tot += 2 * (size_t)(pl->nx + pl->ny) * pl->csize;  // propagator tables
+  }
+  *bytes = tot;
+  return PST_OK;
+}
 
+extern "C" pst_status pst_batch_cache_release(void) {
+  std::lock_guard<std::mutex> lock(g_batch_mu);
+  for (auto& e : g_batch_plans) destroy_batch_plan(e.second);
+  g_batch_plans.clear();
+  return PST_OK;
+}

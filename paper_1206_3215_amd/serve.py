@@ -11,12 +11,19 @@ chunks while the main thread handles arrivals, so admission work (initial
 conditions, host-to-device copies) overlaps with device work.
 
 Executors implement the device side:
-    footprint(req) -> bytes
+    footprint(req) -> bytes      (reserved while the request is admitted)
     admit(req) -> state          (allocate fields, write the initial condition)
-    advance([(state, nsteps)])   (one batched call, returns when done)
-    fetch(state) -> np.ndarray   (result on the host)
+    advance([(state, nsteps)])   (one batched call, returns when done; may
+                                  return one status per work item)
+    fetch(state) -> (np.ndarray, status)   (result on the host)
     release(state)
-`GpuExecutor` is the MI355X one; tests drive the same loop with a CPU one.
+and optionally
+    overhead_bytes() -> bytes    (device memory held beyond the admitted
+                                  requests' reservations, read between chunks)
+    trim()                       (give that memory back)
+A request's status is the worst one reported for it over all its chunks
+(NONFINITE outranks NOT_CONVERGED, which outranks OK).  `GpuExecutor` is the
+MI355X one; tests drive the same loop with a CPU one.
 """
 from __future__ import annotations
 
@@ -29,11 +36,23 @@ import numpy as np
 
 from . import inputs
 
-# Device bytes per grid point of an admitted request (fields + solver
-# workspace), FP32: NLS psi (8) + spectral workspace (8); sine-Gordon two
-# real levels (8) + U, S, W and derivative space (32); Navier-Stokes omega
-# (4) + spectral state and derivative hybrids (36).
-BYTES_PER_POINT = {"nls": 16, "sg": 40, "ns": 40}
+# Device bytes per grid point, FP32 (FP64 doubles them).  Fields of the
+# request: NLS psi (8); sine-Gordon the two levels plus u0, v0 until the
+# start-up step (16); Navier-Stokes omega (4).  Workspace each field takes in
+# the library's cached plan of its size class (solve_batch): the C2C
+# spectrum (8), or 4 half spectra and 4 derivative hybrids (32).
+FIELD_BYTES_PER_POINT = {"nls": 8, "sg": 16, "ns": 4}
+WORKSPACE_BYTES_PER_POINT = {"nls": 8, "sg": 32, "ns": 32}
+# Admission reserves the fields and twice the workspace: a size class's
+# cached plan has room for the next power of two of its group size, so the
+# plans of the admitted requests' classes never exceed this reservation.
+BYTES_PER_POINT = {eq: FIELD_BYTES_PER_POINT[eq] + 2 * WORKSPACE_BYTES_PER_POINT[eq]
+                   for eq in FIELD_BYTES_PER_POINT}
+
+
+def worst_status(a: int, b: int) -> int:
+    """Latch: NONFINITE (6) outranks NOT_CONVERGED (5), which outranks OK."""
+    return max(int(a), int(b))
 
 
 @dataclasses.dataclass
@@ -92,6 +111,7 @@ class Server:
         active: list[Job] = []
         done: list[Job] = []
         used = 0
+        overhead = 0  # executor memory beyond the reservations, read between chunks
         lock = threading.Lock()
         t0 = time.perf_counter()
         now = (lambda: time.perf_counter() - t0) if realtime else (lambda: float("inf"))
@@ -105,7 +125,7 @@ class Server:
             t = now()
             while pending and pending[0].arrival_s <= t:
                 waiting.append(pending.popleft())
-            while waiting and used + self.ex.footprint(waiting[0]) <= self.budget:
+            while waiting and used + overhead + self.ex.footprint(waiting[0]) <= self.budget:
                 r = waiting.popleft()
                 job = Job(r, remaining=r.steps)
                 job.state = self.ex.admit(r)
@@ -119,7 +139,8 @@ class Server:
             with lock:
                 finished = [j for j in active if j.remaining == 0]
             for j in finished:
-                j.result, j.status = self.ex.fetch(j.state)
+                j.result, st = self.ex.fetch(j.state)
+                j.status = worst_status(j.status, st)
                 j.t_done = time.perf_counter() - t0
                 self.ex.release(j.state)
                 used -= self.ex.footprint(j.req)
@@ -127,8 +148,19 @@ class Server:
                     active.remove(j)
                 done.append(j)
 
+        def refresh_overhead():
+            # only between chunks: the executor may have to wait for the device
+            nonlocal overhead
+            if hasattr(self.ex, "overhead_bytes"):
+                overhead = self.ex.overhead_bytes()
+                if overhead and waiting and used + overhead + self.ex.footprint(waiting[0]) > self.budget \
+                        and hasattr(self.ex, "trim"):
+                    self.ex.trim()
+                    overhead = self.ex.overhead_bytes()
+
         while pending or waiting or active:
             retire()
+            refresh_overhead()
             admit_ready()
             with lock:
                 batch = [j for j in active if j.remaining > 0]
@@ -141,10 +173,11 @@ class Server:
             work = [(j.state, min(self.chunk, j.remaining)) for j in batch]
             # the device advances this chunk while arrivals are admitted
             errors = []
+            statuses = []
 
             def chunk():
                 try:
-                    self.ex.advance(work)
+                    statuses.append(self.ex.advance(work))
                 except BaseException as e:  # re-raised on the main thread
                     errors.append(e)
 
@@ -155,8 +188,10 @@ class Server:
                 worker.join(timeout=0.002)
             if errors:
                 raise errors[0]
-            for j, (_, k) in zip(batch, work):
+            per_item = statuses[0] if statuses and statuses[0] is not None else [0] * len(batch)
+            for j, (_, k), st in zip(batch, work, per_item):
                 j.remaining -= k
+                j.status = worst_status(j.status, st)
         wall = time.perf_counter() - t0
         pts = float(sum(j.req.n * j.req.n * j.req.steps for j in done))
         return Report(sorted(done, key=lambda j: j.req.rid), wall, pts)
@@ -190,6 +225,7 @@ class GpuExecutor:
         self.stream = torch.cuda.Stream()          # default priority
         self.copy_stream = torch.cuda.Stream()
         self._sg_plans = {}
+        self._classes = {}  # (eq, n) -> admitted requests of that size class
         p = self.p
         self.params = {
             "nls": binding.make_params("nls", inputs.PAPER_DOMAIN, p.nls_dt, g=1.0),
@@ -201,6 +237,23 @@ class GpuExecutor:
     def footprint(self, req) -> int:
         scale = 2 if self.rdt == self.torch.float64 else 1
         return BYTES_PER_POINT[req.eq] * req.n * req.n * scale
+
+    def overhead_bytes(self) -> int:
+        """Device memory beyond the admitted requests' reservations: cached
+        batch plans of size classes without admitted requests (the others
+        are covered by the reservations) and the sine-Gordon start-up plans'
+        workspaces."""
+        cache = self.b.batch_cache_bytes()
+        reserved = sum(2 * WORKSPACE_BYTES_PER_POINT[eq] * n * n * (2 if self.rdt == self.torch.float64 else 1)
+                       for eq, n in self._active_classes)
+        start = sum(int(p.workspace.numel()) for p in self._sg_plans.values())
+        return max(0, cache - reserved) + start
+
+    def trim(self) -> None:
+        self.stream.synchronize()
+        self.b.batch_cache_release()
+        self._sg_plans.clear()
+        self.torch.cuda.empty_cache()
 
     def admit(self, req):
         torch = self.torch
@@ -220,7 +273,13 @@ class GpuExecutor:
             st["ready"] = torch.cuda.Event()
             st["ready"].record(self.copy_stream)
         st["status"] = torch.zeros(1, dtype=torch.int32, device="cuda")
+        st["class"] = (req.eq, req.n)
+        self._classes[st["class"]] = self._classes.get(st["class"], 0) + 1
         return st
+
+    @property
+    def _active_classes(self):
+        return [c for c, k in self._classes.items() if k > 0]
 
     def advance(self, work):
         torch = self.torch
@@ -255,6 +314,7 @@ class GpuExecutor:
         return out, int(st["status"].item())
 
     def release(self, st):
+        self._classes[st["class"]] -= 1
         st.clear()
 
 

@@ -140,3 +140,130 @@ def test_invalid_requests_rejected_on_host():
     t = to_dev(np.zeros((48, 48)), torch, torch.float32)
     with pytest.raises(b.PstError):
         b.solve_batch([{"eq": "ns", "f0": t, "params": b.make_params("ns", D_NS, 1e-3), "nsteps": 1}])
+
+
+def test_params_change_between_calls_is_not_replayed_stale():
+    # Three calls on the same tensors and schedule capture and replay a graph;
+    # three more with another time step (no host sync between any of them)
+    # must run with the new step: the replay key includes the parameters, and
+    # the propagator tables are rewritten only after the old steps finished.
+    torch = need_gpu()
+    from paper_1206_3215_amd import binding as b
+    f = [inputs.nls_gaussian(128, 128, D_NLS, seed=s) for s in range(3)]
+    u = [inputs.sg_gaussian(64, 64, D_SG, seed=s)[0] for s in range(2)]
+    ts = [to_dev(x, torch, torch.complex128) for x in f]
+    ua = [to_dev(x, torch, torch.float64) for x in u]
+    ub = [to_dev(x * 1.01, torch, torch.float64) for x in u]
+    for dt_nls, dt_sg in ((1e-3, 0.01), (3e-3, 0.02)):
+        pn, ps = b.make_params("nls", D_NLS, dt_nls), b.make_params("sg", D_SG, dt_sg)
+        for _ in range(3):
+            b.solve_batch([{"eq": "nls", "f0": t, "params": pn, "nsteps": 5} for t in ts]
+                          + [{"eq": "sg", "f0": x, "f1": y, "params": ps, "nsteps": 4} for x, y in zip(ua, ub)])
+    torch.cuda.synchronize()
+    plan = b.Plan(128, 128, b.PST_C2C, b.PST_FP64, 1)
+    a = to_dev(f[1][None], torch, torch.complex128)
+    sp = b.Plan(64, 64, b.PST_R2C, b.PST_FP64, 1)
+    x, y = to_dev(u[1][None], torch, torch.float64), to_dev(u[1][None] * 1.01, torch, torch.float64)
+    for dt_nls, dt_sg in ((1e-3, 0.01), (3e-3, 0.02)):
+        for _ in range(3):
+            plan.nls_step(a, D_NLS, dt_nls, 1.0, 5)
+            sp.sg_step(x, y, D_SG, dt_sg, 4)
+    assert np.array_equal(to_host(a)[0], to_host(ts[1]))
+    assert np.array_equal(to_host(x)[0], to_host(ua[1])) and np.array_equal(to_host(y)[0], to_host(ub[1]))
+
+
+def _requests_with_one_nan(torch, b, prec):
+    """A mixed call: NLS, SG, NS fixed-iteration and NS adaptive groups, each
+    with one request whose initial field holds a NaN."""
+    cdt = torch.complex128 if prec else torch.complex64
+    rdt = torch.float64 if prec else torch.float32
+    pn = b.make_params("nls", D_NLS, 1e-3)
+    ps = b.make_params("sg", D_SG, 0.01)
+    pf = b.make_params("ns", D_NS, 1e-3, nu=1e-3, fixed_iters=2)
+    pa = b.make_params("ns", D_NS, 1e-3, nu=1e-3, tol=1e-10)
+    reqs = []
+    for i in range(3):
+        reqs.append({"eq": "nls", "f0": to_dev(inputs.nls_gaussian(64, 64, D_NLS, seed=i), torch, cdt),
+                     "params": pn, "nsteps": 6})
+    for i in range(2):
+        u0 = inputs.sg_gaussian(64, 64, D_SG, seed=i)[0]
+        reqs.append({"eq": "sg", "f0": to_dev(u0, torch, rdt), "f1": to_dev(u0 * 0.99, torch, rdt),
+                     "params": ps, "nsteps": 5})
+    for pr in (pf, pa):
+        for i in range(2):
+            reqs.append({"eq": "ns", "f0": to_dev(inputs.ns_random_phase(32, seed=i), torch, rdt),
+                         "params": pr, "nsteps": 3})
+    bad = [1, 4, 5, 8]
+    for i in bad:
+        reqs[i]["f0"].view(-1)[7] = float("nan")
+    for r in reqs:
+        r["dev_status"] = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    return reqs, bad
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_nonfinite_request_is_reported_and_isolated(prec):
+    torch = need_gpu()
+    from paper_1206_3215_amd import binding as b
+    reqs, bad = _requests_with_one_nan(torch, b, prec)
+    alone, _ = _requests_with_one_nan(torch, b, prec)
+    b.solve_batch(reqs)
+    for r in alone:
+        b.solve_batch([r])
+    torch.cuda.synchronize()
+    for i, (r, a) in enumerate(zip(reqs, alone)):
+        st = int(r["dev_status"].item())
+        assert st == (b.PST_ERR_NONFINITE if i in bad else b.PST_OK), (i, r["eq"], st)
+        assert int(a["dev_status"].item()) == st
+        if i not in bad:
+            assert np.array_equal(to_host(r["f0"]), to_host(a["f0"])), (i, r["eq"])
+
+
+def test_status_latches_across_calls():
+    torch = need_gpu()
+    from paper_1206_3215_amd import binding as b
+    bad = b.make_params("ns", D_NS, 1e-3, nu=1e-3, tol=0.0, max_iter=2)
+    good = b.make_params("ns", D_NS, 1e-3, nu=1e-3, tol=1e-10, max_iter=50)
+    w = to_dev(inputs.ns_random_phase(32, seed=0), torch, torch.float64)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    b.solve_batch([{"eq": "ns", "f0": w, "params": bad, "nsteps": 1, "dev_status": st}])
+    b.solve_batch([{"eq": "ns", "f0": w, "params": good, "nsteps": 2, "dev_status": st}])
+    torch.cuda.synchronize()
+    assert int(st.item()) == b.PST_ERR_NOT_CONVERGED
+    st.zero_()
+    b.solve_batch([{"eq": "ns", "f0": w, "params": good, "nsteps": 2, "dev_status": st}])
+    torch.cuda.synchronize()
+    assert int(st.item()) == b.PST_OK
+
+
+def test_nonfinite_latched_for_single_plan_entry_points():
+    torch = need_gpu()
+    from paper_1206_3215_amd import binding as b
+    plan = b.Plan(64, 64, b.PST_C2C, b.PST_FP32, 2)
+    psi = to_dev(np.stack([inputs.nls_gaussian(64, 64, D_NLS, seed=s) for s in range(2)]), torch,
+                 torch.complex64)
+    plan.nls_step(psi, D_NLS, 1e-3, 1.0, 3)
+    assert plan.sync_status() == b.PST_OK
+    psi[1, 5, 5] = float("inf")
+    plan.nls_step(psi, D_NLS, 1e-3, 1.0, 3)
+    assert plan.sync_status() == b.PST_ERR_NONFINITE
+    assert plan.sync_status() == b.PST_OK                 # read clears it
+    sp = b.Plan(64, 64, b.PST_R2C, b.PST_FP64, 1)
+    u = to_dev(inputs.sg_gaussian(64, 64, D_SG, seed=0)[0][None], torch, torch.float64)
+    v = u.clone()
+    v[0, 3, 3] = float("nan")
+    sp.sg_step(u, v, D_SG, 0.01, 2)
+    assert sp.sync_status() == b.PST_ERR_NONFINITE
+
+
+def test_misaligned_fields_rejected():
+    torch = need_gpu()
+    from paper_1206_3215_amd import binding as b
+    buf = torch.zeros(64 * 64 + 1, dtype=torch.complex128, device="cuda")
+    off = buf[1:].view(64, 64)                            # 16 bytes past a 256-byte boundary
+    assert off.data_ptr() % 256 != 0
+    with pytest.raises(b.PstError, match="aligned"):
+        b.solve_batch([{"eq": "nls", "f0": off, "params": b.make_params("nls", D_NLS, 1e-3), "nsteps": 1}])
+    plan = b.Plan(64, 64, b.PST_C2C, b.PST_FP64, 1)
+    with pytest.raises(b.PstError, match="aligned"):
+        plan.nls_step(off.view(1, 64, 64), D_NLS, 1e-3, 1.0, 1)

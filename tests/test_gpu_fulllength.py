@@ -1,0 +1,170 @@
+"""Parity at the full length of the benchmark workloads, against reference
+samples of the FP64 oracle (written by tests/golden/gen_refs.py, which runs
+only the oracle).  The device result is sampled at the index sets stored in
+each file and compared element by element; the error is
+max |gpu - ref| / max |ref| over the samples, with max |ref| taken over the
+whole reference field.  Tolerances: 1e-4 for FP32 runs, 1e-11 for FP64."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1206_3215_amd import inputs
+from tests.gpuutil import need_gpu, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+TOL = {0: 1e-4, 1: 1e-11}
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+EPS32 = 2.0 ** -23
+
+
+def ref(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} not generated (python tests/golden/gen_refs.py)")
+    return np.load(path)
+
+
+def sample_err(f, r, prefix, key=""):
+    """Max sample deviation of field f from reference file r over the stored
+    rows, columns, lattice and window, relative to max |ref|."""
+    lines = r[f"{key}lines"]
+    w0, w = int(r[f"{key}win0"]), int(r[f"{key}win"])
+    got = {"rows": f[lines, :], "cols": f[:, lines],
+           "lat": f[np.ix_(r[f"{key}lat_y"], r[f"{key}lat_x"])], "win": f[w0:w0 + w, w0:w0 + w]}
+    scale = float(r[f"{prefix}maxabs"])
+    return max(float(np.max(np.abs(got[k] - r[f"{prefix}{k}"]))) for k in got) / scale
+
+
+# ------------------------------------------------------------------ NLS ---
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", [1, 0])
+def test_nls_4096_thousand_steps(prec):
+    # The headline workload: 4096^2 on [-5pi,5pi)^2, dt 1e-3, g = +1, 1000
+    # steps, in chunks of 100 with FP64 mass and energy after each.
+    torch = need_gpu()
+    from paper_1206_3215_amd import binding as b
+    r = ref("ref_nls_4096_1000.npz")
+    n, dt, d = int(r["n"]), float(r["dt"]), inputs.PAPER_DOMAIN
+    plan = b.Plan(n, n, b.PST_C2C, prec, 1)
+    plan.autotune("nls")
+    psi = to_dev(inputs.nls_gaussian(n, n, d, seed=int(r["seed"]))[None], torch, plan.complex_dtype)
+    q = [plan.conserved_quantities("nls", psi, d=d, dt=dt, g=1.0)[0]]
+    for _ in range(int(r["steps"]) // 100):
+        plan.nls_step(psi, d, dt, 1.0, 100)
+        q.append(plan.conserved_quantities("nls", psi, d=d, dt=dt, g=1.0)[0])
+    assert plan.sync_status() == b.PST_OK
+    got = to_host(psi)[0]
+    err = sample_err(got, r, "")
+    series = r["series"]                       # (step, mass, energy) every 100 steps
+    mass = np.array([x[0] for x in q])
+    energy = np.array([x[1] for x in q])
+    print(f"prec={prec} rel_err={err:.3e} mass drift={mass[-1] / mass[0] - 1:.3e} "
+          f"energy vs oracle={energy[-1] / series[-1, 2] - 1:.3e}")
+    assert err < TOL[prec]
+    assert abs(float(np.max(np.abs(got))) / float(r["maxabs"]) - 1) < TOL[prec]
+    # mass and energy at every 100 steps against the oracle's, within the
+    # field's tolerance class
+    assert np.max(np.abs(mass / series[:, 1] - 1)) < TOL[prec]
+    assert np.max(np.abs(energy / series[:, 2] - 1)) < TOL[prec]
+    if prec == 1:
+        # the split step conserves mass to rounding (Results, NLS subsection)
+        assert np.max(np.abs(mass / mass[0] - 1)) < 1e-12
+    else:
+        # FP32 reading: every step is a product of unit-modulus factors, each
+        # rounded once, so the mass may drift by at most one single-precision
+        # rounding unit per step
+        steps = series[:, 0]
+        assert np.all(np.abs(mass / mass[0] - 1) <= EPS32 * np.maximum(steps, 1))
+
+
+# ------------------------------------------------------------ sine-Gordon ---
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sg_2048_batch_of_16_full_length(prec):
+    # 16 seeds of 2048^2 in one launch, start-up plus 499 steps of dt 0.01;
+    # seeds 0 and 11 against the oracle, and their Hamiltonians.
+    torch = need_gpu()
+    from paper_1206_3215_amd import binding as b
+    r = ref("ref_sg_2048_500.npz")
+    n, dt, d, steps = int(r["n"]), float(r["dt"]), inputs.PAPER_DOMAIN, int(r["steps"])
+    plan = b.Plan(n, n, b.PST_R2C, prec, 16)
+    plan.autotune("sg")
+    u0 = to_dev(np.stack([inputs.sg_gaussian(n, n, d, seed=s)[0] for s in range(16)]), torch, plan.real_dtype)
+    up, uc = torch.empty_like(u0), torch.empty_like(u0)
+    plan.sg_start(u0, torch.zeros_like(u0), up, uc, d, dt)
+    del u0
+    h0 = plan.conserved_quantities("sg", up, uc, d=d, dt=dt)
+    plan.sg_step(up, uc, d, dt, steps)
+    h1 = plan.conserved_quantities("sg", up, uc, d=d, dt=dt)
+    assert plan.sync_status() == b.PST_OK
+    for s in (int(x) for x in r["seeds"]):
+        e_prev = sample_err(to_host(up[s]), r, f"s{s}_prev_")
+        e_curr = sample_err(to_host(uc[s]), r, f"s{s}_curr_")
+        H0, H1 = r[f"s{s}_H0"], r[f"s{s}_H1"]      # (kinetic, gradient, potential, total)
+        print(f"prec={prec} seed={s} err prev={e_prev:.3e} curr={e_curr:.3e} "
+              f"H {h0[s, 0]:.12g} -> {h1[s, 0]:.12g} (oracle {H0[3]:.12g} -> {H1[3]:.12g})")
+        assert e_prev < TOL[prec] and e_curr < TOL[prec]
+        # Hamiltonian at both ends against the oracle's, within the field's
+        # tolerance class, and its drift over the run equal to the oracle's
+        assert abs(h0[s, 0] / H0[3] - 1) < TOL[prec] and abs(h1[s, 0] / H1[3] - 1) < TOL[prec]
+        drift_gpu, drift_ref = h1[s, 0] / h0[s, 0] - 1, H1[3] / H0[3] - 1
+        assert abs(drift_gpu - drift_ref) < 2 * TOL[prec]
+        # Results, sine-Gordon subsection: the Hamiltonian holds 6 significant
+        # figures over the run wherever the oracle's does at this step size
+        if abs(drift_ref) < 5e-7:
+            assert abs(drift_gpu) < 5e-7 + 2 * TOL[prec]
+
+
+# ----------------------------------------------------------- Navier-Stokes ---
+def _ns_run_batch(torch, b, r, prec, chunks):
+    """The uneven batch (seeds 0-3 at 1024^2, 4-7 at 2048^2) through
+    solve_batch, adaptive fixed point, advanced by the step counts in chunks;
+    returns fields after each chunk and the per-request statuses."""
+    rdt = torch.float64 if prec else torch.float32
+    seeds = [int(x) for x in r["seeds"]]
+    fields = [to_dev(inputs.ns_random_phase(int(r[f"s{s}_n"]), seed=s), torch, rdt) for s in seeds]
+    pr = b.make_params("ns", inputs.NS_DOMAIN, float(r["dt"]), nu=float(r["nu"]), tol=float(r["tol"]),
+                       max_iter=int(r["max_iter"]))
+    st = [torch.zeros(1, dtype=torch.int32, device="cuda") for _ in seeds]
+    snaps = []
+    for k in chunks:
+        b.solve_batch([{"eq": "ns", "f0": f, "params": pr, "nsteps": k, "dev_status": s}
+                       for f, s in zip(fields, st)])
+        torch.cuda.synchronize()
+        snaps.append([to_host(f) for f in fields])
+    return seeds, snaps, [int(s.item()) for s in st]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", [1, 0])
+def test_ns_uneven_batch_against_oracle_within_horizon(prec):
+    # 4 x 1024^2 + 4 x 2048^2 random-phase vorticity, nu 1e-3, dt 2.5e-4,
+    # tol 1e-10, adaptive, through solve_batch: every field against the
+    # oracle at steps 40 and 240, inside the predictability horizon measured
+    # by the twin experiment (tests/golden/ns_twin_1024.json); energy and
+    # enstrophy at the end.
+    torch = need_gpu()
+    from paper_1206_3215_amd import binding as b
+    r = ref("ref_ns_uneven.npz")
+    t1, t2 = (int(x) for x in r["steps"])
+    seeds, snaps, status = _ns_run_batch(torch, b, r, prec, [t1, t2 - t1])
+    assert status == [b.PST_OK] * len(seeds)
+    worst = 0.0
+    for i, s in enumerate(seeds):
+        for t, snap in ((t1, snaps[0]), (t2, snaps[1])):
+            e = sample_err(snap[i], r, f"s{s}_t{t}_", key=f"s{s}_")
+            worst = max(worst, e)
+            assert e < TOL[prec], (s, t, e)
+    print(f"prec={prec} worst rel_err={worst:.3e}")
+    # energy and enstrophy of the final fields against the oracle's series
+    n0 = int(r[f"s{seeds[0]}_n"])
+    for i, s in enumerate(seeds):
+        n = int(r[f"s{s}_n"])
+        plan = b.Plan(n, n, b.PST_R2C, prec, 1)
+        q = plan.conserved_quantities("ns", to_dev(snaps[1][i][None], torch, plan.real_dtype), d=inputs.NS_DOMAIN)
+        ser = r[f"s{s}_series"][t2]
+        assert abs(q[0, 0] / ser[1] - 1) < TOL[prec] and abs(q[0, 1] / ser[2] - 1) < TOL[prec], (s, q, ser)
+        del plan
+    assert n0 == 1024
+

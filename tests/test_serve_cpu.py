@@ -112,3 +112,67 @@ def test_failure_is_isolated():
 def test_request_larger_than_budget_rejected():
     with pytest.raises(ValueError):
         Server(OracleExecutor(), budget_bytes=100).run([inputs.Request(0, "nls", 16, 3, 0.0)])
+
+
+class ChunkStatusExecutor(OracleExecutor):
+    """Reports NOT_CONVERGED for one request on its first chunk only (the
+    per-chunk statuses a device executor would return), OK at fetch."""
+
+    def __init__(self, rid):
+        super().__init__()
+        self.rid = rid
+        self.reported = False
+
+    def advance(self, work):
+        super().advance(work)
+        out = []
+        for st, _ in work:
+            hit = st["req"].rid == self.rid and not self.reported
+            self.reported = self.reported or hit
+            out.append(5 if hit else 0)
+        return out
+
+    def fetch(self, st):
+        return super().fetch(st)[0], 0
+
+
+def test_status_is_latched_over_chunks():
+    reqs = small_mix(6)
+    rid = max(reqs, key=lambda r: r.steps).rid          # runs for several chunks
+    rep = Server(ChunkStatusExecutor(rid), budget_bytes=10 ** 9, chunk=2).run(reqs, realtime=False)
+    for j in rep.jobs:
+        assert j.status == (5 if j.req.rid == rid else 0)
+
+
+class OverheadExecutor(OracleExecutor):
+    """Holds device memory beyond the reservations (a library cache) that
+    only trim() gives back."""
+
+    def __init__(self, extra):
+        super().__init__()
+        self.extra = extra
+        self.trims = 0
+        self.peak_total = 0
+
+    def admit(self, req):
+        st = super().admit(req)
+        self.peak_total = max(self.peak_total, self.in_use + self.extra)
+        return st
+
+    def overhead_bytes(self):
+        return self.extra
+
+    def trim(self):
+        self.trims += 1
+        self.extra = 0
+
+
+def test_executor_overhead_counts_against_budget():
+    reqs = small_mix(10)
+    budget = 4 * BYTES_PER_POINT["sg"] * 32 * 32
+    ex = OverheadExecutor(extra=budget // 2)
+    rep = Server(ex, budget_bytes=budget, chunk=3).run(reqs, realtime=False)
+    assert len(rep.jobs) == 10 and ex.peak_total <= budget
+    assert ex.trims >= 1                                 # released when admission was blocked
+    for j in rep.jobs:
+        np.testing.assert_array_equal(j.result, solo(j.req))
