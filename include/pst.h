@@ -226,41 +226,70 @@ const char* pst_last_error(void);
 /* Library version string. */
 const char* pst_version(void);
 
-/* Column tile variants.  Column passes (lines along y) run W adjacent
- * columns per block.  Variant 0, the default, exists for every length n:
- * the widest W that fits 1024 threads and 150 KB of LDS, 16 values of a line
- * per thread, complex values exchanged through LDS between stages.
- * Single-field column passes (NLS steps and C2C transforms) of FP32 lines of
- * 4096 and more have two more variants that let two blocks share a CU:
+/* Tile variants (not in the paper, which observed that launch parameters
+ * chosen by the compiler ran 2x slower and that autotuning would help).
+ *
+ * Column passes (lines along y) run W adjacent columns per block.  Variant
+ * 0, the default, exists for every length n: the widest W that fits 1024
+ * threads and 150 KB of LDS, 16 values of a line per thread, complex values
+ * exchanged through LDS between stages, radix 16.  For two-line passes
+ * (sine-Gordon, Navier-Stokes, real transforms) and for single-field passes
+ * shorter than 4096, variant 1 is half of variant 0's W.  Single-field
+ * column passes (NLS steps and C2C transforms) of lines of 4096 and more add,
+ * in FP32:
  *   1: the same W, 32 values per thread, real and imaginary parts exchanged
- *      one after the other (half the threads and half the LDS per block);
- *   2: the same W, 16 values per thread, the split exchange, registers
- *      capped so that two 1024-thread blocks fit a CU;
- *   3: twice the W, 32 values per thread, the split exchange (wider row
- *      segments per block, one block per CU).
- * For every other pass and length, variant 1 is half of variant 0's W;
- * single-field passes of FP64 lines of 4096 and more add
- *   2: variant 0's W, 32 values per thread, the split exchange (half the
- *      threads and half the LDS, so that two blocks share a CU).
+ *      one after the other ("split": half the threads and half the LDS);
+ *   2: the same W, 16 values per thread, split, registers capped so that two
+ *      1024-thread blocks fit a CU;
+ *   3: twice the W, 32 values per thread, split;
+ *   4: the same W, 16 values per thread, split, no register cap;
+ * and in FP64:
+ *   1: half of variant 0's W;
+ *   2: variant 0's W, 32 values per thread, split;
+ *   3: variant 0's W, 16 values per thread, split;
+ *   4: twice variant 0's W, 16 values per thread, split (full 128-byte row
+ *      segments);
+ *   5: variant 0's W, radix 8 with 8 values per thread, split.
  * pst_column_variant_info reports (columns per block, values per thread,
- * split exchange 0/1) of variant for length n; single_field != 0 asks about
+ * split 0/1, radix) of variant for length n; single_field != 0 asks about
  * the single-field passes.  PST_ERR_INVALID if n is not a supported length
  * or the variant does not exist. */
 pst_status pst_column_variant_info(pst_prec prec, int n, int variant, int single_field, int* columns,
-                                   int* values_per_thread, int* split);
+                                   int* values_per_thread, int* split, int* radix);
 
-/* Autotuning (not in the paper, which notes that launch parameters chosen
- * by the compiler ran 2x slower and that autotuning would help): times the
- * column pass of equation eq on this plan with each column variant on
- * workspace data, keeps the fastest in the plan and remembers it for later
- * plans of the same (eq, precision, nx, ny) in this process.  Synchronises.
- * *chosen (may be NULL) receives the variant. */
+/* Row variants of the NLS in-place row pass (the pass of every step; the
+ * entry and exit passes keep the default).  Lines of 4096 and more run one
+ * line per block: 0, 16 values per thread with the complex exchange (32
+ * values, split, at 8192); 1, 16 values, split; 2, radix 8 with 8 values per
+ * thread, split; 3, radix 8, complex exchange.  Shorter lines run row pairs,
+ * P per block: 0, the default P (256 threads); then P/2 (where P >= 2) and
+ * 2P (where it fits 1024 threads and 150 KB of LDS), numbered in that
+ * order.  pst_row_variant_info
+ * reports (row pairs per block, 0 for one line per block; values per thread;
+ * split; radix).  Variants with the same radix and values per thread give
+ * bit-identical results; the others differ by rounding. */
+pst_status pst_row_variant_info(pst_prec prec, int n, int variant, int* pairs_per_block,
+                                int* values_per_thread, int* split, int* radix);
+
+/* Autotuning: times the column pass of equation eq on this plan in each
+ * column variant, and for NLS the in-place row pass in each row variant, on
+ * workspace data; keeps the fastest in the plan and remembers them for
+ * later plans of the same (eq, precision, nx, ny) in this process, so that
+ * every plan of that class runs the same variants.  Synchronises.  *chosen
+ * (may be NULL) receives the column variant. */
 pst_status pst_autotune(pst_plan plan, pst_eq eq, int* chosen);
 
 /* Column variant used by this plan's column passes of length ny (0 by
  * default).  PST_ERR_INVALID if the variant does not exist for ny and the
  * plan's kind (C2C plans: single-field variants; R2C plans: two-line). */
 pst_status pst_set_column_variant(pst_plan plan, int variant);
+
+/* Row variant of this plan's NLS in-place row pass (0 by default; R2C
+ * plans have only variant 0).  PST_ERR_INVALID if it does not exist. */
+pst_status pst_set_row_variant(pst_plan plan, int variant);
+
+/* The plan's current (row, column) variants. */
+pst_status pst_get_variants(pst_plan plan, int* row_variant, int* column_variant);
 
 /* Per-pass timing.  While enabled, every pass kernel that plan launches is
  * bracketed by a pair of HIP events recorded on the plan's stream.

@@ -77,7 +77,11 @@ _SIGS = {
     "pst_autotune": [_vp, C.c_int, C.POINTER(C.c_int)],
     "pst_set_column_variant": [_vp, C.c_int],
     "pst_column_variant_info": [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
-                                C.POINTER(C.c_int)],
+                                C.POINTER(C.c_int), C.POINTER(C.c_int)],
+    "pst_row_variant_info": [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                             C.POINTER(C.c_int), C.POINTER(C.c_int)],
+    "pst_set_row_variant": [_vp, C.c_int],
+    "pst_get_variants": [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int)],
     "pst_profile_enable": [_vp, C.c_int],
     "pst_profile_read": [_vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)],
     "pst_last_error": [],
@@ -262,9 +266,18 @@ class Plan:
     def set_column_variant(self, variant: int) -> None:
         check(lib.pst_set_column_variant(self.handle, int(variant)), "pst_set_column_variant")
 
+    def set_row_variant(self, variant: int) -> None:
+        check(lib.pst_set_row_variant(self.handle, int(variant)), "pst_set_row_variant")
+
+    def variants(self) -> tuple:
+        """(row variant, column variant) the plan runs."""
+        r, c = C.c_int(), C.c_int()
+        check(lib.pst_get_variants(self.handle, C.byref(r), C.byref(c)), "pst_get_variants")
+        return r.value, c.value
+
     def column_variants(self) -> list:
-        """[(columns per block, values per thread, split)] of every column
-        variant compiled for this plan's ny and kind, by variant number."""
+        """[(columns per block, values per thread, split, radix)] of every
+        column variant compiled for this plan's ny and kind, by number."""
         return column_variants(self.prec, self.ny, self.kind == PST_C2C)
 
     def profile_enable(self, on: bool = True) -> None:
@@ -283,12 +296,22 @@ class Plan:
 
 
 def column_variants(prec: int, n: int, single_field: bool) -> list:
-    """[(columns per block, values per thread, split)] by variant number."""
+    """[(columns per block, values per thread, split, radix)] by variant number."""
     out = []
-    w, v, sp = C.c_int(), C.c_int(), C.c_int()
+    w, v, sp, r = C.c_int(), C.c_int(), C.c_int(), C.c_int()
     while lib.pst_column_variant_info(prec, n, len(out), int(single_field), C.byref(w), C.byref(v),
-                                      C.byref(sp)) == 0:
-        out.append((w.value, v.value, sp.value))
+                                      C.byref(sp), C.byref(r)) == 0:
+        out.append((w.value, v.value, sp.value, r.value))
+    return out
+
+
+def row_variants(prec: int, n: int) -> list:
+    """[(row pairs per block (0: one line per block), values per thread,
+    split, radix)] of the NLS in-place row pass by variant number."""
+    out = []
+    p, v, sp, r = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+    while lib.pst_row_variant_info(prec, n, len(out), C.byref(p), C.byref(v), C.byref(sp), C.byref(r)) == 0:
+        out.append((p.value, v.value, sp.value, r.value))
     return out
 
 

@@ -16,6 +16,11 @@
 // (Ns r)), computed in double precision on the host and rounded once.  The
 // inverse transform multiplies by their conjugates.  Transforms are
 // unnormalised: forward kernel exp(-i...), inverse exp(+i...).
+//
+// The radix R of the full stages is a template parameter: 16 by default,
+// or 8 (lines of 64 and more), which halves the values a thread must hold
+// for one butterfly at the cost of one more exchange.  A length's table
+// holds the radix-16 layout followed by the radix-8 one.
 #pragma once
 
 #include <type_traits>
@@ -50,9 +55,17 @@ __host__ __device__ constexpr int stage_tw_offset(int N, int R, int s) {
   for (int i = 1; i < s; ++i) off += (stage_radix(N, R, i) - 1) * stage_ns(N, R, i);
   return off;
 }
-__host__ __device__ constexpr int twiddle_table_len(int N) {
-  return stage_tw_offset(N, line_radix(N), num_stages(N, line_radix(N)));
+__host__ __device__ constexpr int twiddle_table_len(int N, int R) {
+  return stage_tw_offset(N, R, num_stages(N, R));
 }
+__host__ __device__ constexpr int twiddle_table_len(int N) { return twiddle_table_len(N, line_radix(N)); }
+// Lengths that carry the radix-8 layout as well.
+__host__ __device__ constexpr bool has_radix8(int N) { return N >= 64; }
+// Entries of a length's table, and where the layout of radix R starts.
+__host__ __device__ constexpr int tw_table_total(int N) {
+  return twiddle_table_len(N) + (has_radix8(N) ? twiddle_table_len(N, 8) : 0);
+}
+__host__ __device__ constexpr int tw_base(int N, int R) { return R == line_radix(N) ? 0 : twiddle_table_len(N); }
 
 // LDS slot of element e of a line: one pad slot every 16 elements.  A
 // column tile interleaves its WS lines (slot * WS + line), so the lanes of a
@@ -241,16 +254,16 @@ __host__ __device__ __forceinline__ cpx<T> tw_load(const cpx<T>* tw, int len, un
 // go to the line's LDS slots.  SPLIT exchanges real parts, then imaginary
 // parts, through a buffer of scalars (half the LDS); the imaginary outputs
 // wait in the consumed input registers meanwhile.
-template <int N, int S, bool INV, int WS, int VPT, bool SPLIT, typename T>
+template <int N, int S, bool INV, int WS, int VPT, bool SPLIT, int R, typename T>
 __host__ __device__ __forceinline__ void line_stage(cpx<T> (&v)[VPT], void* ldsv, int t,
                                                     const cpx<T>* __restrict__ tw) {
-  constexpr int R = line_radix(N);
+  static_assert(R == line_radix(N) || (R == 8 && has_radix8(N)), "no twiddle layout for this radix");
   constexpr int TL = N / VPT;
   constexpr int r = stage_radix(N, R, S);
   constexpr int Ns = stage_ns(N, R, S);
   constexpr int B = VPT / r;
   constexpr bool last = (S == num_stages(N, R) - 1);
-  constexpr int toff = stage_tw_offset(N, R, S);
+  constexpr int toff = tw_base(N, R) + stage_tw_offset(N, R, S);
   static_assert(VPT % r == 0, "values per thread must be a multiple of each radix");
 #pragma unroll
   for (int b = 0; b < B; ++b) {
@@ -263,7 +276,7 @@ __host__ __device__ __forceinline__ void line_stage(cpx<T> (&v)[VPT], void* ldsv
 #pragma unroll
       for (int q = 1; q < r; ++q) {
         // uniform base toff + (q-1) Ns, per-lane offset k
-        const cpx<T> c = tw_load(tw, twiddle_table_len(N), k, (unsigned)(toff + (q - 1) * Ns));
+        const cpx<T> c = tw_load(tw, tw_table_total(N), k, (unsigned)(toff + (q - 1) * Ns));
         w[q] = INV ? cmul_conj(w[q], c) : cmul(w[q], c);
       }
     }
@@ -291,9 +304,8 @@ __host__ __device__ __forceinline__ void line_stage(cpx<T> (&v)[VPT], void* ldsv
 
 // Second half of a split exchange: the imaginary outputs parked in v[].im go
 // to the same slots the real parts used.
-template <int N, int S, int WS, int VPT, typename T>
+template <int N, int S, int WS, int VPT, int R, typename T>
 __host__ __device__ __forceinline__ void line_stage_im(const cpx<T> (&v)[VPT], T* lds, int t) {
-  constexpr int R = line_radix(N);
   constexpr int TL = N / VPT;
   constexpr int r = stage_radix(N, R, S);
   constexpr int Ns = stage_ns(N, R, S);
@@ -327,23 +339,23 @@ __host__ __device__ __forceinline__ void line_read_part(cpx<T> (&v)[VPT], const 
   }
 }
 
-template <int N, int S, bool INV, int WS, int VPT, bool SPLIT, typename T>
+template <int N, int S, bool INV, int WS, int VPT, bool SPLIT, int R, typename T>
 __device__ __forceinline__ void line_stages(cpx<T> (&v)[VPT], void* lds, int t, const cpx<T>* __restrict__ tw) {
-  if constexpr (S < num_stages(N, line_radix(N))) {
-    line_stage<N, S, INV, WS, VPT, SPLIT>(v, lds, t, tw);
-    if constexpr (S < num_stages(N, line_radix(N)) - 1) {
+  if constexpr (S < num_stages(N, R)) {
+    line_stage<N, S, INV, WS, VPT, SPLIT, R>(v, lds, t, tw);
+    if constexpr (S < num_stages(N, R) - 1) {
       __syncthreads();
       if constexpr (SPLIT) {
         line_read_part<N, WS, VPT, false>(v, static_cast<const T*>(lds), t);
         __syncthreads();
-        line_stage_im<N, S, WS, VPT>(v, static_cast<T*>(lds), t);
+        line_stage_im<N, S, WS, VPT, R>(v, static_cast<T*>(lds), t);
         __syncthreads();
         line_read_part<N, WS, VPT, true>(v, static_cast<const T*>(lds), t);
       } else {
         line_read<N, WS, VPT>(v, static_cast<const cpx<T>*>(lds), t);
       }
       __syncthreads();
-      line_stages<N, S + 1, INV, WS, VPT, SPLIT>(v, lds, t, tw);
+      line_stages<N, S + 1, INV, WS, VPT, SPLIT, R>(v, lds, t, tw);
     }
   }
 }
@@ -352,9 +364,10 @@ __device__ __forceinline__ void line_stages(cpx<T> (&v)[VPT], void* lds, int t, 
 // (every thread of the block must call it: it contains block barriers).
 // lds points at the line's first slot (complex, or scalar when SPLIT); WS is
 // the slot stride (lines per interleaved tile).
-template <int N, bool INV, int WS = 1, int VPT = line_radix(N), bool SPLIT = false, typename T>
+template <int N, bool INV, int WS = 1, int VPT = line_radix(N), bool SPLIT = false, int R = line_radix(N),
+          typename T>
 __device__ __forceinline__ void line_fft(cpx<T> (&v)[VPT], void* lds, int t, const cpx<T>* __restrict__ tw) {
-  line_stages<N, 0, INV, WS, VPT, SPLIT>(v, lds, t, tw);
+  line_stages<N, 0, INV, WS, VPT, SPLIT, R>(v, lds, t, tw);
 }
 
 }  // namespace pst

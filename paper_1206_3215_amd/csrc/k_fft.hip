@@ -29,7 +29,7 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_row_c2c(
 }
 
 // --------------------------------------------------------- C2C columns ---
-template <typename T, int N, bool INV, int WT, int VPT, bool SPLIT, int WPE>
+template <typename T, int N, bool INV, int WT, int VPT, bool SPLIT, int WPE, int R>
 __global__ __launch_bounds__((WT * (N / VPT))) __attribute__((amdgpu_waves_per_eu(WPE))) void k_col_c2c(
     const cpx<T>* src, cpx<T>* dst, int ncols, int ld, int tiles_per_field, T scale, const cpx<T>* __restrict__ tw) {
   using G = ColGeom<T, N, WT, VPT, SPLIT>;
@@ -49,7 +49,7 @@ __global__ __launch_bounds__((WT * (N / VPT))) __attribute__((amdgpu_waves_per_e
   cpx<T> v[G::R];
 #pragma unroll
   for (int s = 0; s < G::R; ++s) v[s] = in.template ldc<T>(o0, s * ds);
-  line_fft<N, INV, WT, VPT, SPLIT>(v, L, t, tw);
+  line_fft<N, INV, WT, VPT, SPLIT, R>(v, L, t, tw);
   if (valid) {
 #pragma unroll
     for (int s = 0; s < G::R; ++s) out.st(o0, s * ds, v[s] * scale);
@@ -178,8 +178,8 @@ static hipError_t col_c2c(int ny, int ncols, int ld, int nfields, const void* sr
       using C = decltype(cfg);
       using G = ColGeom<T, N, C::w, C::vpt, C::split>;
       const int tiles = (ncols + C::w - 1) / C::w;
-      auto* k = inv ? &k_col_c2c<T, N, true, C::w, C::vpt, C::split, C::wpe>
-                    : &k_col_c2c<T, N, false, C::w, C::vpt, C::split, C::wpe>;
+      auto* k = inv ? &k_col_c2c<T, N, true, C::w, C::vpt, C::split, C::wpe, C::radix>
+                    : &k_col_c2c<T, N, false, C::w, C::vpt, C::split, C::wpe, C::radix>;
       allow_lds(k, G::LDS_BYTES);
       hipLaunchKernelGGL(k, dim3(tiles * nfields), dim3(G::THREADS), G::LDS_BYTES, s, (const cpx<T>*)src,
                          (cpx<T>*)dst, ncols, ld, tiles, (T)scale, (const cpx<T>*)tw);
@@ -235,13 +235,14 @@ hipError_t fft_row_c2r(Prec p, int n, int nlines, int ny, const void* in, FieldR
                   : row_c2r<double>(n, nlines, ny, in, out, scale, tw, s);
 }
 
-bool col_variant_info(Prec p, int n, int var, bool single, int* w, int* vpt, int* split) {
+bool col_variant_info(Prec p, int n, int var, bool single, int* w, int* vpt, int* split, int* radix) {
   bool found = false;
   auto get = [&](auto cfg) {
     using C = decltype(cfg);
     *w = C::w;
     *vpt = C::vpt;
     *split = C::split ? 1 : 0;
+    *radix = C::radix;
     found = true;
   };
   dispatch_n(n, [&](auto nc) {
@@ -250,7 +251,7 @@ bool col_variant_info(Prec p, int n, int var, bool single, int* w, int* vpt, int
       if (p == P32) dispatch_col1<float, N>(var, get);
       else dispatch_col1<double, N>(var, get);
     } else {
-      auto getw = [&](auto wc) { get(ColCfg<decltype(wc)::value, line_radix(N), false>{}); };
+      auto getw = [&](auto wc) { get(ColCfg<decltype(wc)::value, line_radix(N), false, 1, line_radix(N)>{}); };
       if (p == P32) dispatch_w<float, N>(var, getw);
       else dispatch_w<double, N>(var, getw);
     }

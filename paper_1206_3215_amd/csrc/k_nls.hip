@@ -29,20 +29,20 @@ namespace pst {
 // tile.  MODE 0 reads plain rows of psi, MODE 2 writes them; everything else
 // is in the pair-interleaved layout.  UNI: all pairs of a block lie in one
 // field, reached through a buffer resource.
-template <typename T, int N, int VPT, bool SPLIT>
+template <typename T, int N, int VPT, bool SPLIT, int P_ = 0>
 struct PairGeom {
   static constexpr int R = VPT;
   static constexpr int TL = N / VPT;
-  static constexpr int P = TL >= 128 ? 1 : 128 / TL;
+  static constexpr int P = P_ > 0 ? P_ : TL >= 128 ? 1 : 128 / TL;
   static constexpr int THREADS = 2 * P * TL;
   static constexpr int LINE = lds_line_len(N);
   static constexpr size_t LDS_BYTES = (size_t)P * 2 * LINE * (SPLIT ? sizeof(T) : sizeof(cpx<T>));
 };
 
-template <typename T, int N, int MODE, int VPT, bool SPLIT, bool UNI>
-__global__ __launch_bounds__((PairGeom<T, N, VPT, SPLIT>::THREADS)) void k_nls_row(
+template <typename T, int N, int MODE, int VPT, bool SPLIT, bool UNI, int P_>
+__global__ __launch_bounds__((PairGeom<T, N, VPT, SPLIT, P_>::THREADS)) void k_nls_row(
     FieldRef psi, int npairs, int lny, T phase_coef, T scale, const cpx<T>* __restrict__ tw, StatusRef st) {
-  using G = PairGeom<T, N, VPT, SPLIT>;
+  using G = PairGeom<T, N, VPT, SPLIT, P_>;
   extern __shared__ char smem[];
   const int l = threadIdx.x & 1, q = threadIdx.x >> 1;
   const int t = q % G::TL, pl = q / G::TL;
@@ -113,7 +113,7 @@ __global__ __launch_bounds__((PairGeom<T, N, VPT, SPLIT>::THREADS)) void k_nls_r
   }
 }
 
-template <typename T, int N, int WT, int VPT, bool SPLIT, int WPE>
+template <typename T, int N, int WT, int VPT, bool SPLIT, int WPE, int R>
 __global__ __launch_bounds__((WT * (N / VPT))) __attribute__((amdgpu_waves_per_eu(WPE))) void k_nls_col(
     FieldRef psi, int nx, int tiles_per_field, const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ ex,
     const cpx<T>* __restrict__ ey, T scale) {
@@ -140,7 +140,7 @@ __global__ __launch_bounds__((WT * (N / VPT))) __attribute__((amdgpu_waves_per_e
   cpx<T> v[G::R];
 #pragma unroll
   for (int s = 0; s < G::R; ++s) v[s] = fb.template ldc<T>(voff(s), soff(s));
-  line_fft<N, false, WT, VPT, SPLIT>(v, L, t, tw);
+  line_fft<N, false, WT, VPT, SPLIT, R>(v, L, t, tw);
   // the propagator loads are issued after the forward transform: hoisted
   // above it they would hold registers through the whole transform
   asm volatile("" ::: "memory");
@@ -151,7 +151,7 @@ __global__ __launch_bounds__((WT * (N / VPT))) __attribute__((amdgpu_waves_per_e
     const cpx<T> wx = w + cmul(w, exm);
     v[s] = wx + cmul(wx, ey[t + s * G::TL]);
   }
-  line_fft<N, true, WT, VPT, SPLIT>(v, L, t, tw);
+  line_fft<N, true, WT, VPT, SPLIT, R>(v, L, t, tw);
   if (valid) {
 #pragma unroll
     for (int s = 0; s < G::R; ++s) fb.st(voff(s), soff(s), v[s]);
@@ -163,7 +163,7 @@ __global__ __launch_bounds__((WT * (N / VPT))) __attribute__((amdgpu_waves_per_e
 // pair's span.  Blocks are
 // mapped to lines so that each XCD takes a contiguous range of lines: the
 // two lines of a pair run side by side on one XCD and share its L2.
-template <typename T, int N, int MODE, int VPT, bool SPLIT>
+template <typename T, int N, int MODE, int VPT, bool SPLIT, int R>
 __global__ __launch_bounds__((N / VPT)) void k_nls_row1(FieldRef psi, int lny, T phase_coef, T scale,
                                                          const cpx<T>* __restrict__ tw) {
   constexpr int TL = N / VPT;
@@ -183,16 +183,16 @@ __global__ __launch_bounds__((N / VPT)) void k_nls_row1(FieldRef psi, int lny, T
 #pragma unroll
   for (int s = 0; s < VPT; ++s) v[s] = fb.template ldc<T>(i0 * sz, s * ids * sz);
   if constexpr (MODE == 0) {
-    line_fft<N, false, 1, VPT, SPLIT>(v, L, t, tw);
+    line_fft<N, false, 1, VPT, SPLIT, R>(v, L, t, tw);
 #pragma unroll
     for (int s = 0; s < VPT; ++s) v[s] = v[s] * scale;
   } else if constexpr (MODE == 1) {
-    line_fft<N, true, 1, VPT, SPLIT>(v, L, t, tw);
+    line_fft<N, true, 1, VPT, SPLIT, R>(v, L, t, tw);
 #pragma unroll
     for (int s = 0; s < VPT; ++s) v[s] = rotate_neg(v[s], phase_coef * norm2(v[s]));
-    line_fft<N, false, 1, VPT, SPLIT>(v, L, t, tw);
+    line_fft<N, false, 1, VPT, SPLIT, R>(v, L, t, tw);
   } else {
-    line_fft<N, true, 1, VPT, SPLIT>(v, L, t, tw);
+    line_fft<N, true, 1, VPT, SPLIT, R>(v, L, t, tw);
 #pragma unroll
     for (int s = 0; s < VPT; ++s) v[s] = v[s] * scale;
   }
@@ -210,53 +210,85 @@ struct NlsRowCfg {
   static constexpr bool SPLIT = BIG;
 };
 
-template <typename T, int N, int MODE, bool UNI>
+template <typename T, int N, int MODE, bool UNI, int VPT, bool SPLIT, int P>
 static void launch_row(int npairs, int ny, FieldRef psi, double pc, double scale, const void* tw, hipStream_t s,
                        StatusRef st) {
-  using C = NlsRowCfg<T, N>;
-  using G = PairGeom<T, N, C::VPT, C::SPLIT>;
-  auto* k = &k_nls_row<T, N, MODE, C::VPT, C::SPLIT, UNI>;
+  using G = PairGeom<T, N, VPT, SPLIT, P>;
+  auto* k = &k_nls_row<T, N, MODE, VPT, SPLIT, UNI, P>;
   allow_lds(k, G::LDS_BYTES);
   hipLaunchKernelGGL(k, dim3((npairs + G::P - 1) / G::P), dim3(G::THREADS), G::LDS_BYTES, s, psi, npairs,
                      ilog2c(ny), (T)pc, (T)scale, (const cpx<T>*)tw, st);
 }
 
+// Row pass of mode 0 (entry), 1 (the in-place step pass, in row variant
+// var) or 2 (exit).  The entry and exit passes convert between layouts, so a
+// pair's two rows must be owned by one block: they run the pair kernel in
+// its default configuration (32 values per thread and the split exchange
+// for lines of 8192).
 template <typename T>
 static hipError_t row(int nx, int nlines, int ny, FieldRef psi, int mode, double pc, double scale,
-                      const void* tw, hipStream_t s, StatusRef st) {
+                      const void* tw, hipStream_t s, StatusRef st, int var) {
   if (ny % 2 != 0 || nlines % 2 != 0) return hipErrorInvalidValue;
-  bool ok = dispatch_n(nx, [&](auto nc) {
+  bool ok = false;
+  dispatch_n(nx, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
     using C = NlsRowCfg<T, N>;
-    constexpr int P = PairGeom<T, N, C::VPT, C::SPLIT>::P;
-    const bool uni = 2 * P <= ny;
-    auto go = [&](auto m) {
+    auto pairs = [&](auto m, auto cfg) {
       constexpr int MODE = decltype(m)::value;
-      // (only the in-place interleaved pass: the entry and exit passes convert
-      // between layouts, and a pair's two rows must then be owned by one block)
-      if constexpr (MODE == 1 && N / C::VPT >= 256) {
-        auto* k = &k_nls_row1<T, N, MODE, C::VPT, C::SPLIT>;
-        constexpr size_t lds = (size_t)lds_line_len(N) * (C::SPLIT ? sizeof(T) : sizeof(cpx<T>));
-        allow_lds(k, lds);
-        hipLaunchKernelGGL(k, dim3(nlines), dim3(N / C::VPT), lds, s, psi, ilog2c(ny), (T)pc, (T)scale,
-                           (const cpx<T>*)tw);
-      } else if (uni) {
-        launch_row<T, N, MODE, true>(nlines / 2, ny, psi, pc, scale, tw, s, st);
-      } else {
-        launch_row<T, N, MODE, false>(nlines / 2, ny, psi, pc, scale, tw, s, st);
-      }
+      using RC = decltype(cfg);
+      constexpr int P = PairGeom<T, N, RC::vpt, RC::split, RC::pairs>::P;
+      if (2 * P <= ny) launch_row<T, N, MODE, true, RC::vpt, RC::split, RC::pairs>(nlines / 2, ny, psi, pc, scale, tw, s, st);
+      else launch_row<T, N, MODE, false, RC::vpt, RC::split, RC::pairs>(nlines / 2, ny, psi, pc, scale, tw, s, st);
+      ok = true;
     };
-    if (mode == 0) go(IntC<0>{});
-    else if (mode == 1) go(IntC<1>{});
-    else go(IntC<2>{});
+    if (mode == 0) {
+      pairs(IntC<0>{}, RowCfg<C::VPT, C::SPLIT, line_radix(N), 0>{});
+    } else if (mode == 2) {
+      pairs(IntC<2>{}, RowCfg<C::VPT, C::SPLIT, line_radix(N), 0>{});
+    } else {
+      dispatch_nls_row<T, N>(var, [&](auto cfg) {
+        using RC = decltype(cfg);
+        if constexpr (NlsRowShape<N>::ONE_LINE) {
+          // one line per block, mapped so that each XCD takes a contiguous
+          // range of lines (the two lines of a pair share its L2)
+          auto* k = &k_nls_row1<T, N, 1, RC::vpt, RC::split, RC::radix>;
+          constexpr size_t lds = (size_t)lds_line_len(N) * (RC::split ? sizeof(T) : sizeof(cpx<T>));
+          allow_lds(k, lds);
+          hipLaunchKernelGGL(k, dim3(nlines), dim3(N / RC::vpt), lds, s, psi, ilog2c(ny), (T)pc, (T)scale,
+                             (const cpx<T>*)tw);
+          ok = true;
+        } else {
+          pairs(IntC<1>{}, cfg);
+        }
+      });
+    }
   });
   return ok ? hipGetLastError() : hipErrorInvalidValue;
 }
 
 hipError_t nls_row(Prec p, int nx, int nlines, int ny, FieldRef psi, int mode, double phase_coef, double scale,
-                   const void* tw, hipStream_t s, StatusRef st) {
-  return p == P32 ? row<float>(nx, nlines, ny, psi, mode, phase_coef, scale, tw, s, st)
-                  : row<double>(nx, nlines, ny, psi, mode, phase_coef, scale, tw, s, st);
+                   const void* tw, hipStream_t s, StatusRef st, int var) {
+  return p == P32 ? row<float>(nx, nlines, ny, psi, mode, phase_coef, scale, tw, s, st, var)
+                  : row<double>(nx, nlines, ny, psi, mode, phase_coef, scale, tw, s, st, var);
+}
+
+bool nls_row_variant_info(Prec p, int n, int var, int* pairs, int* vpt, int* split, int* radix) {
+  bool found = false;
+  dispatch_n(n, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    auto get = [&](auto cfg) {
+      using RC = decltype(cfg);
+      // pairs: row pairs per block, 0 for one line per block
+      *pairs = NlsRowShape<N>::ONE_LINE ? 0 : PairGeom<float, N, RC::vpt, RC::split, RC::pairs>::P;
+      *vpt = RC::vpt;
+      *split = RC::split ? 1 : 0;
+      *radix = RC::radix;
+      found = true;
+    };
+    if (p == P32) dispatch_nls_row<float, N>(var, get);
+    else dispatch_nls_row<double, N>(var, get);
+  });
+  return found;
 }
 
 template <typename T>
@@ -269,7 +301,7 @@ static hipError_t col(int ny, int nx, int nfields, FieldRef psi, const void* tw,
       using C = decltype(cfg);
       using G = ColGeom<T, N, C::w, C::vpt, C::split>;
       const int tiles = (nx + C::w - 1) / C::w;
-      auto* k = &k_nls_col<T, N, C::w, C::vpt, C::split, C::wpe>;
+      auto* k = &k_nls_col<T, N, C::w, C::vpt, C::split, C::wpe, C::radix>;
       allow_lds(k, G::LDS_BYTES);
       hipLaunchKernelGGL(k, dim3(tiles * nfields), dim3(G::THREADS), G::LDS_BYTES, s, psi, nx, tiles,
                          (const cpx<T>*)tw, (const cpx<T>*)ex, (const cpx<T>*)ey, (T)(1.0 / ((double)nx * N)));

@@ -52,16 +52,18 @@ struct ColGeom {
 // one per plan).  Variant 0: the largest W with W*N/16 <= 1024 threads,
 // W <= 16 and <= 150 KB of LDS, 16 values per thread, complex exchange.
 // Single-field passes (NLS, C2C) of FP32 lines of 4096 and more, whose
-// variant-0 block fills a CU alone, add two variants that let two blocks
-// share a CU: 1, the same W with 32 values per thread and the split
-// exchange (half the threads and half the LDS); 2, the same W with 16
-// values per thread, the split exchange and registers capped for 8 waves
-// per SIMD; and one that widens the row segments a block reads and writes:
-// 3, twice the W with 32 values per thread and the split exchange (variant
-// 0's threads and LDS).  Otherwise variant 1 is half of variant 0's W, and
-// single-field FP64 passes of 4096 and more add 2, variant 0's W with 32
-// values per thread and the split exchange (half the LDS, two blocks per
-// CU, registers capped for 2 waves per SIMD).
+// variant-0 block fills a CU alone, add variants that let two blocks share
+// a CU or widen the row segments: 1, the same W with 32 values per thread
+// and the split exchange (half the threads and half the LDS); 2, the same W
+// with 16 values per thread, the split exchange and registers capped for 8
+// waves per SIMD; 3, twice the W with 32 values per thread and the split
+// exchange (variant 0's threads and LDS); 4, variant 2 without the register
+// cap.  Otherwise variant 1 is half of variant 0's W, and single-field FP64
+// passes of 4096 and more add 2, variant 0's W with 32 values per thread
+// and the split exchange (registers capped for 2 waves per SIMD); 3, variant
+// 0's W with the split exchange (two blocks per CU); 4, twice that W (full
+// 128-byte row segments, one 1024-thread block per CU); 5, variant 0's W at
+// radix 8 (8 values per thread, twice the threads) with the split exchange.
 template <typename T, int N>
 struct ColTiles {
   static constexpr int TL = N / line_radix(N);
@@ -74,11 +76,12 @@ struct ColTiles {
   static constexpr bool SPLIT2 = std::is_same<T, double>::value && N >= 4096;
 };
 
-// W columns per block, VPT values per thread, split exchange, and the
-// minimum waves per SIMD the register allocation must allow (1: no cap).
-template <int W, int VPT, bool SPLIT, int WPE = 1>
+// W columns per block, VPT values per thread, split exchange, the minimum
+// waves per SIMD the register allocation must allow (1: no cap), radix of
+// the full stages.
+template <int W, int VPT, bool SPLIT, int WPE = 1, int R = 16>
 struct ColCfg {
-  static constexpr int w = W, vpt = VPT, wpe = WPE;
+  static constexpr int w = W, vpt = VPT, wpe = WPE, radix = R;
   static constexpr bool split = SPLIT;
 };
 
@@ -88,7 +91,7 @@ bool dispatch_col1(int var, F&& f) {
   using CT = ColTiles<T, N>;
   constexpr int R = line_radix(N);
   if (var == 0) {
-    f(ColCfg<CT::WMAX, R, false>{});
+    f(ColCfg<CT::WMAX, R, false, 1, R>{});
     return true;
   }
   if constexpr (CT::SPLIT1) {
@@ -104,14 +107,98 @@ bool dispatch_col1(int var, F&& f) {
       f(ColCfg<2 * CT::WMAX, 32, true>{});
       return true;
     }
+    if (var == 4) {
+      f(ColCfg<CT::WMAX, R, true>{});
+      return true;
+    }
   } else if (var == 1) {
-    f(ColCfg<CT::WALT, R, false>{});
+    f(ColCfg<CT::WALT, R, false, 1, R>{});
     return true;
   }
   if constexpr (CT::SPLIT2) {
     if (var == 2) {
       f(ColCfg<CT::WMAX, 32, true, 2>{});
       return true;
+    }
+    if (var == 3) {
+      f(ColCfg<CT::WMAX, 16, true>{});
+      return true;
+    }
+    if (var == 4) {
+      f(ColCfg<2 * CT::WMAX, 16, true>{});
+      return true;
+    }
+    if (var == 5) {
+      f(ColCfg<CT::WMAX, 8, true, 1, 8>{});
+      return true;
+    }
+  }
+  return false;
+}
+
+// Row variants of the NLS in-place row pass (the pass that runs every step),
+// for lines of length N.  Lines of 4096 and more run one line per block:
+// 0, 16 values per thread and the complex exchange (32 values and the split
+// exchange at 8192); 1, 16 values and the split exchange (half the LDS);
+// 2, radix 8 with 8 values per thread (twice the threads, fewer registers)
+// and the split exchange; 3, radix 8 with the complex exchange.  Shorter
+// lines run row pairs, P pairs per block: 0, the default P (256 threads);
+// then half of it (where P >= 2) and twice it (where that fits 1024 threads
+// and 150 KB of LDS), numbered in that order.  P = 0 in a config means the
+// default.
+template <int VPT, bool SPLIT, int R, int P>
+struct RowCfg {
+  static constexpr int vpt = VPT, radix = R, pairs = P;
+  static constexpr bool split = SPLIT;
+};
+template <int N>
+struct NlsRowShape {
+  static constexpr bool ONE_LINE = N / line_radix(N) >= 256;  // one line per block
+  static constexpr int TL = N / line_radix(N);
+  static constexpr int P0 = TL >= 128 ? 1 : 128 / TL;          // default pairs per block
+};
+template <typename T, int N, class F>
+bool dispatch_nls_row(int var, F&& f) {
+  using S = NlsRowShape<N>;
+  constexpr int R = line_radix(N);
+  if constexpr (S::ONE_LINE) {
+    if (var == 0) {
+      if constexpr (N >= 8192) f(RowCfg<32, true, 16, 0>{});
+      else f(RowCfg<16, false, 16, 0>{});
+      return true;
+    }
+    if (var == 1) {
+      f(RowCfg<16, true, 16, 0>{});
+      return true;
+    }
+    if (var == 2) {
+      f(RowCfg<8, true, 8, 0>{});
+      return true;
+    }
+    if (var == 3) {
+      f(RowCfg<8, false, 8, 0>{});
+      return true;
+    }
+  } else {
+    if (var == 0) {
+      f(RowCfg<R, false, R, 0>{});
+      return true;
+    }
+    // the others are numbered in order of those that exist
+    int k = 1;
+    if constexpr (S::P0 >= 2) {
+      if (var == k) {
+        f(RowCfg<R, false, R, S::P0 / 2>{});
+        return true;
+      }
+      ++k;
+    }
+    constexpr size_t lds2 = (size_t)4 * S::P0 * lds_line_len(N) * sizeof(cpx<T>);
+    if constexpr (4 * S::P0 * S::TL <= 1024 && lds2 <= 150 * 1024) {
+      if (var == k) {
+        f(RowCfg<R, false, R, 2 * S::P0>{});
+        return true;
+      }
     }
   }
   return false;
@@ -313,9 +400,21 @@ __device__ __forceinline__ cpx<float> rotate_neg(cpx<float> v, float th) {
   return cpx<float>{v.re + (v.re * cm1 + v.im * s), v.im + (v.im * cm1 - v.re * s)};
 }
 __device__ __forceinline__ cpx<double> rotate_neg(cpx<double> v, double th) {
-  double sh, ch;
-  sincos(0.5 * th, &sh, &ch);
-  const double cm1 = -2.0 * sh * sh, s = 2.0 * sh * ch;
+  double cm1, s;
+  if (fabs(th) <= 0.03125) {
+    // |theta| <= 2^-5: Taylor series of cos - 1 to theta^10 and of sin to
+    // theta^11; the first omitted terms are below 2^-110 and 2^-104
+    // relative to cos - 1 and sin (under double rounding), and the series
+    // costs a dozen FMAs against the library routine's range reduction
+    const double t2 = th * th;
+    cm1 = t2 * (-0.5 + t2 * (1.0 / 24 + t2 * (-1.0 / 720 + t2 * (1.0 / 40320 + t2 * (-1.0 / 3628800)))));
+    s = th * (1.0 + t2 * (-1.0 / 6 + t2 * (1.0 / 120 + t2 * (-1.0 / 5040 + t2 * (1.0 / 362880 + t2 * (-1.0 / 39916800))))));
+  } else {
+    double sh, ch;
+    sincos(0.5 * th, &sh, &ch);
+    cm1 = -2.0 * sh * sh;
+    s = 2.0 * sh * ch;
+  }
   return cpx<double>{v.re + (v.re * cm1 + v.im * s), v.im + (v.im * cm1 - v.re * s)};
 }
 

@@ -38,12 +38,15 @@ struct StatusRef {
   int* const* field = nullptr;
 };
 
-// Column-pass tiles compiled for length n: the widest (W columns per block,
-// bounded by the block size and the LDS footprint) and its half.
 // Column tile variant `var` for lines of length n: columns per block,
-// values per thread, split exchange.  single: a single-field pass (NLS,
-// C2C); two-line passes have no split variants.  False if not compiled.
-bool col_variant_info(Prec p, int n, int var, bool single, int* w, int* vpt, int* split);
+// values per thread, split exchange, radix.  single: a single-field pass
+// (NLS, C2C); two-line passes have no split or radix variants.  False if
+// not compiled.
+bool col_variant_info(Prec p, int n, int var, bool single, int* w, int* vpt, int* split, int* radix);
+// Row variant `var` of the NLS in-place row pass for lines of length n: row
+// pairs per block (0: one line per block), values per thread, split
+// exchange, radix.  False if not compiled.
+bool nls_row_variant_info(Prec p, int n, int var, int* pairs, int* vpt, int* split, int* radix);
 
 // ----------------------------------------------------------------- FFT ---
 // Row pass over nlines contiguous complex lines of length n: out = FFT(in)
@@ -69,9 +72,9 @@ hipError_t fft_row_c2r(Prec p, int n, int nlines, int ny, const void* in, FieldR
 // mode 0: H = nx * FFT_x(psi); 1: H <- FFT_x(e^{-i c |iFFT_x H|^2} iFFT_x H);
 // 2: psi = iFFT_x(H) / nx.  phase_coef = g dt / nx^2, scale as stated.
 // Mode 2 latches ST_NONFINITE into st for a field whose result holds a
-// non-finite value.
+// non-finite value.  var selects the row variant of mode 1.
 hipError_t nls_row(Prec p, int nx, int nlines, int ny, FieldRef psi, int mode, double phase_coef,
-                   double scale, const void* tw, hipStream_t s, StatusRef st = StatusRef());
+                   double scale, const void* tw, hipStream_t s, StatusRef st = StatusRef(), int var = 0);
 // Column: FFT_y, multiply by (1 + ex[mx]) (1 + ey[my]) / (nx ny), iFFT_y (in place).
 hipError_t nls_col(Prec p, int ny, int nx, int nfields, FieldRef psi, const void* tw,
                    const void* ex, const void* ey, int W, hipStream_t s);

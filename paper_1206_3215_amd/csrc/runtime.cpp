@@ -37,21 +37,26 @@ pst_status hip_check(hipError_t e, const char* what) {
 
 static bool pow2_in_range(int n) { return n >= 4 && n <= 8192 && (n & (n - 1)) == 0; }
 
-// Twiddle table of the line FFT of length n (layout in fft_line.hpp), in
+// Twiddle table of the line FFT of length n (layout in fft_line.hpp: the
+// stages of the default radix, then those of radix 8 where compiled), in
 // double precision, rounded once to the plan's precision.
 static std::vector<std::complex<double>> twiddles(int n) {
-  const int R = line_radix(n);
-  std::vector<std::complex<double>> tab(twiddle_table_len(n) > 0 ? twiddle_table_len(n) : 1);
-  for (int s = 1; s < num_stages(n, R); ++s) {
-    const int r = stage_radix(n, R, s), ns = stage_ns(n, R, s), off = stage_tw_offset(n, R, s);
-    const long M = (long)ns * r;
-    for (int q = 1; q < r; ++q)
-      for (int k = 0; k < ns; ++k) {
-        const long m = ((long)q * k) % M;
-        const double ang = -2.0 * M_PI * (double)m / (double)M;
-        tab[off + (q - 1) * ns + k] = {std::cos(ang), std::sin(ang)};
-      }
-  }
+  std::vector<std::complex<double>> tab(tw_table_total(n) > 0 ? tw_table_total(n) : 1);
+  auto fill = [&](int R) {
+    const int base = tw_base(n, R);
+    for (int s = 1; s < num_stages(n, R); ++s) {
+      const int r = stage_radix(n, R, s), ns = stage_ns(n, R, s), off = base + stage_tw_offset(n, R, s);
+      const long M = (long)ns * r;
+      for (int q = 1; q < r; ++q)
+        for (int k = 0; k < ns; ++k) {
+          const long m = ((long)q * k) % M;
+          const double ang = -2.0 * M_PI * (double)m / (double)M;
+          tab[off + (q - 1) * ns + k] = {std::cos(ang), std::sin(ang)};
+        }
+    }
+  };
+  fill(line_radix(n));
+  if (has_radix8(n)) fill(8);
   return tab;
 }
 
@@ -322,21 +327,52 @@ pst_status fft2d_exec(pst_plan pl, const void* in, void* out, int sign) {
 
 pst_status pst_set_column_variant(pst_plan pl, int variant) {
   if (pl == nullptr) return fail(PST_ERR_INVALID, "plan is NULL");
-  int w, v, sp;
-  if (!col_variant_info(pl->P, pl->ny, variant, pl->kind == PST_C2C, &w, &v, &sp))
+  int w, v, sp, r;
+  if (!col_variant_info(pl->P, pl->ny, variant, pl->kind == PST_C2C, &w, &v, &sp, &r))
     return fail(PST_ERR_INVALID, "column variant %d is not compiled for ny=%d", variant, pl->ny);
   pl->colvar = variant;
   return PST_OK;
 }
 
+pst_status pst_set_row_variant(pst_plan pl, int variant) {
+  if (pl == nullptr) return fail(PST_ERR_INVALID, "plan is NULL");
+  int p, v, sp, r;
+  if (pl->kind != PST_C2C) {
+    if (variant != 0) return fail(PST_ERR_INVALID, "R2C plans have only row variant 0");
+  } else if (!nls_row_variant_info(pl->P, pl->nx, variant, &p, &v, &sp, &r)) {
+    return fail(PST_ERR_INVALID, "row variant %d is not compiled for nx=%d", variant, pl->nx);
+  }
+  pl->rowvar = variant;
+  return PST_OK;
+}
+
+pst_status pst_get_variants(pst_plan pl, int* row_variant, int* column_variant) {
+  if (pl == nullptr || row_variant == nullptr || column_variant == nullptr)
+    return fail(PST_ERR_INVALID, "NULL argument");
+  *row_variant = pl->rowvar;
+  *column_variant = pl->colvar;
+  return PST_OK;
+}
+
 pst_status pst_column_variant_info(pst_prec prec, int n, int variant, int single_field, int* columns,
-                                   int* values_per_thread, int* split) {
+                                   int* values_per_thread, int* split, int* radix) {
   if (prec != PST_FP32 && prec != PST_FP64) return fail(PST_ERR_INVALID, "unknown precision %d", (int)prec);
-  if (columns == nullptr || values_per_thread == nullptr || split == nullptr)
+  if (columns == nullptr || values_per_thread == nullptr || split == nullptr || radix == nullptr)
     return fail(PST_ERR_INVALID, "output pointer is NULL");
   if (!col_variant_info(prec == PST_FP32 ? P32 : P64, n, variant, single_field != 0, columns, values_per_thread,
-                        split))
+                        split, radix))
     return fail(PST_ERR_INVALID, "no column variant %d for length %d", variant, n);
+  return PST_OK;
+}
+
+pst_status pst_row_variant_info(pst_prec prec, int n, int variant, int* pairs_per_block, int* values_per_thread,
+                                int* split, int* radix) {
+  if (prec != PST_FP32 && prec != PST_FP64) return fail(PST_ERR_INVALID, "unknown precision %d", (int)prec);
+  if (pairs_per_block == nullptr || values_per_thread == nullptr || split == nullptr || radix == nullptr)
+    return fail(PST_ERR_INVALID, "output pointer is NULL");
+  if (!nls_row_variant_info(prec == PST_FP32 ? P32 : P64, n, variant, pairs_per_block, values_per_thread, split,
+                            radix))
+    return fail(PST_ERR_INVALID, "no row variant %d for length %d", variant, n);
   return PST_OK;
 }
 

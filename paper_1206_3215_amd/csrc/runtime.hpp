@@ -29,6 +29,7 @@ struct pst_plan_s {
   int device = 0;
   size_t csize = 8, rsize = 4;  // bytes per complex / real element
   int colvar = 0;               // column tile variant for length ny
+  int rowvar = 0;               // row variant of the NLS in-place row pass (length nx)
   void* tw_x = nullptr;         // twiddles of the x lines (length nx)
   void* tw_y = nullptr;         // twiddles of the y lines (length ny)
   int* dstatus = nullptr;       // latched device status bits

@@ -92,7 +92,9 @@ static pst_status nls_run(Plan* pl, FieldRef psi, const pst_nls_params* p, int n
   hipStream_t s = pl->stream;
   auto row = [&](int mode, double pc_, double scale) {
     if (mode == 1) prof_begin(pl, PST_PASS_NLS_ROW);
-    pst_status r = hip_check(nls_row(pl->P, nx, lines, ny, psi, mode, pc_, scale, pl->tw_x, s), "nls row");
+    pst_status r = hip_check(nls_row(pl->P, nx, lines, ny, psi, mode, pc_, scale, pl->tw_x, s, StatusRef(),
+                                     pl->rowvar),
+                             "nls row");
     if (mode == 1) prof_end(pl);
     return r;
   };
@@ -462,11 +464,33 @@ pst_status ns_step(pst_plan pl, void* omega, const pst_ns_params* p, int nsteps,
 }  // extern "C"
 
 // ------------------------------------------------------------ autotune ---
-extern "C" pst_status pst_autotune(pst_plan pl, pst_eq eq, int* chosen);
+extern "C" pst_status pst_autotune(pst_plan plan, pst_eq eq, int* chosen);
 namespace {
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int>, int> g_tuned;  // (eq, prec, nx, ny) -> variant
+// (eq, prec, nx, ny) -> (row variant, column variant): every plan of a class
+// in the process runs the same variants, so results do not depend on which
+// plan (or batch) a field is stepped in
+std::map<std::tuple<int, int, int, int>, std::pair<int, int>> g_tuned;
 }  // namespace
+
+// Average time of `launch` over 5 launches after one warm-up.
+template <class L>
+static pst_status time_launch(Plan* pl, L&& launch, float* ms) {
+  hipStream_t s = pl->stream;
+  TRY(hip_check(launch(), "autotune warm-up"));
+  hipEvent_t a, b;
+  TRY(hip_check(hipEventCreate(&a), "hipEventCreate"));
+  TRY(hip_check(hipEventCreate(&b), "hipEventCreate"));
+  hipEventRecord(a, s);
+  pst_status st = PST_OK;
+  for (int i = 0; i < 5 && st == PST_OK; ++i) st = hip_check(launch(), "autotune launch");
+  hipEventRecord(b, s);
+  if (st == PST_OK) st = hip_check(hipEventSynchronize(b), "hipEventSynchronize");
+  if (st == PST_OK) st = hip_check(hipEventElapsedTime(ms, a, b), "hipEventElapsedTime");
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return st;
+}
 
 // ptab: zeroed propagator stand-in of max(nx, ny) complex entries.
 static pst_status time_col(Plan* pl, pst_eq eq, int w, const void* ptab, float* ms) {
@@ -493,19 +517,17 @@ static pst_status time_col(Plan* pl, pst_eq eq, int w, const void* ptab, float* 
     // the iteration pass (mode 2), which runs several times per step
     return ns_col(pl->P, 2, ny, B, P, S, static_cast<int*>(ws_at(pl, pl->off_nsstate)), pl->tw_y, w, s);
   };
-  TRY(hip_check(launch(), "autotune warm-up"));
-  hipEvent_t a, b;
-  TRY(hip_check(hipEventCreate(&a), "hipEventCreate"));
-  TRY(hip_check(hipEventCreate(&b), "hipEventCreate"));
-  hipEventRecord(a, s);
-  pst_status st = PST_OK;
-  for (int i = 0; i < 5 && st == PST_OK; ++i) st = hip_check(launch(), "autotune launch");
-  hipEventRecord(b, s);
-  if (st == PST_OK) st = hip_check(hipEventSynchronize(b), "hipEventSynchronize");
-  if (st == PST_OK) st = hip_check(hipEventElapsedTime(ms, a, b), "hipEventElapsedTime");
-  hipEventDestroy(a);
-  hipEventDestroy(b);
-  return st;
+  return time_launch(pl, launch, ms);
+}
+
+// The NLS in-place row pass in row variant v on workspace data.
+static pst_status time_row(Plan* pl, int v, float* ms) {
+  const int nx = pl->nx, ny = pl->ny, B = pl->batch;
+  auto launch = [&]() -> hipError_t {
+    return nls_row(pl->P, nx, B * ny, ny, contiguous(ws_at(pl, pl->off_spec), (size_t)nx * ny * pl->csize), 1,
+                   1e-9, 1.0, pl->tw_x, pl->stream, StatusRef(), v);
+  };
+  return time_launch(pl, launch, ms);
 }
 
 extern "C" pst_status pst_autotune(pst_plan pl, pst_eq eq, int* chosen) {
@@ -518,7 +540,8 @@ extern "C" pst_status pst_autotune(pst_plan pl, pst_eq eq, int* chosen) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) {
-      pl->colvar = it->second;
+      pl->rowvar = it->second.first;
+      pl->colvar = it->second.second;
       if (chosen) *chosen = pl->colvar;
       return PST_OK;
     }
@@ -530,10 +553,10 @@ extern "C" pst_status pst_autotune(pst_plan pl, pst_eq eq, int* chosen) {
   TRY(hip_check(hipMalloc(&ptab, pbytes), "hipMalloc(autotune table)"));
   pl->owned.push_back(ptab);
   TRY(hip_check(hipMemsetAsync(ptab, 0, pbytes, pl->stream), "clear autotune table"));
-  int best = 0;
+  int best = 0, best_row = 0;
   float best_ms = 1e30f;
-  int w, q, sp;
-  for (int v = 0; col_variant_info(pl->P, pl->ny, v, eq == PST_NLS, &w, &q, &sp); ++v) {
+  int w, q, sp, r;
+  for (int v = 0; col_variant_info(pl->P, pl->ny, v, eq == PST_NLS, &w, &q, &sp, &r); ++v) {
     float ms = 0.f;
     TRY(time_col(pl, eq, v, ptab, &ms));
     if (ms < best_ms) {
@@ -541,10 +564,22 @@ extern "C" pst_status pst_autotune(pst_plan pl, pst_eq eq, int* chosen) {
       best = v;
     }
   }
+  if (eq == PST_NLS) {
+    best_ms = 1e30f;
+    for (int v = 0; nls_row_variant_info(pl->P, pl->nx, v, &w, &q, &sp, &r); ++v) {
+      float ms = 0.f;
+      TRY(time_row(pl, v, &ms));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_row = v;
+      }
+    }
+  }
   pl->colvar = best;
+  pl->rowvar = best_row;
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    g_tuned[key] = best;
+    g_tuned[key] = std::make_pair(best_row, best);
   }
   if (chosen) *chosen = best;
   return PST_OK;

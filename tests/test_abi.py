@@ -60,32 +60,54 @@ def test_entry_points_reject_null_plan(lib):
 
 
 def test_column_variant_table_on_host(lib):
-    # the compiled column tiles follow the stated rules: variant 0 fills 1024
-    # threads / 150 KB of LDS; single-field FP32 passes of 4096 and more add
-    # the 32-values-per-thread split variants; anything else has variant 1 =
-    # half of variant 0's width, and single-field FP64 passes of 4096 and more
-    # add variant 2 (32 values per thread, split); unknown variants and sizes
-    # are rejected
+    # the compiled column tiles follow the rules stated in pst.h: variant 0
+    # fills 1024 threads / 150 KB of LDS; single-field passes of 4096 and
+    # more add the split / wide / radix-8 variants; anything else has variant
+    # 1 = half of variant 0's width; unknown variants and sizes are rejected
     from paper_1206_3215_amd import binding as b
-    assert b.column_variants(b.PST_FP32, 4096, True) == [(4, 16, 0), (4, 32, 1), (4, 16, 1), (8, 32, 1)]
-    assert b.column_variants(b.PST_FP32, 8192, True) == [(2, 16, 0), (2, 32, 1), (2, 16, 1), (4, 32, 1)]
-    assert b.column_variants(b.PST_FP32, 4096, False) == [(4, 16, 0), (2, 16, 0)]
-    assert b.column_variants(b.PST_FP64, 4096, True) == [(2, 16, 0), (1, 16, 0), (2, 32, 1)]
-    assert b.column_variants(b.PST_FP64, 8192, True) == [(1, 16, 0), (1, 16, 0), (1, 32, 1)]
-    assert b.column_variants(b.PST_FP64, 2048, True) == [(4, 16, 0), (2, 16, 0)]
-    assert b.column_variants(b.PST_FP32, 1024, True) == [(16, 16, 0), (8, 16, 0)]
-    assert b.column_variants(b.PST_FP32, 16, True) == [(16, 16, 0), (8, 16, 0)]
+    assert b.column_variants(b.PST_FP32, 4096, True) == [(4, 16, 0, 16), (4, 32, 1, 16), (4, 16, 1, 16),
+                                                         (8, 32, 1, 16), (4, 16, 1, 16)]
+    assert b.column_variants(b.PST_FP32, 8192, True) == [(2, 16, 0, 16), (2, 32, 1, 16), (2, 16, 1, 16),
+                                                         (4, 32, 1, 16), (2, 16, 1, 16)]
+    assert b.column_variants(b.PST_FP32, 4096, False) == [(4, 16, 0, 16), (2, 16, 0, 16)]
+    assert b.column_variants(b.PST_FP64, 4096, True) == [(2, 16, 0, 16), (1, 16, 0, 16), (2, 32, 1, 16),
+                                                         (2, 16, 1, 16), (4, 16, 1, 16), (2, 8, 1, 8)]
+    assert b.column_variants(b.PST_FP64, 8192, True) == [(1, 16, 0, 16), (1, 16, 0, 16), (1, 32, 1, 16),
+                                                         (1, 16, 1, 16), (2, 16, 1, 16), (1, 8, 1, 8)]
+    assert b.column_variants(b.PST_FP64, 2048, True) == [(4, 16, 0, 16), (2, 16, 0, 16)]
+    assert b.column_variants(b.PST_FP32, 1024, True) == [(16, 16, 0, 16), (8, 16, 0, 16)]
+    assert b.column_variants(b.PST_FP32, 16, True) == [(16, 16, 0, 16), (8, 16, 0, 16)]
     for prec in (b.PST_FP32, b.PST_FP64):
         for e in range(2, 14):
             n = 1 << e
             for single in (True, False):
-                for w, vpt, split in b.column_variants(prec, n, single):
+                for w, vpt, split, radix in b.column_variants(prec, n, single):
                     r = min(n, vpt)
                     esz = (4 if split else 8) * (2 if prec == b.PST_FP64 else 1)
                     assert w * (n // r) <= 1024 and w * (n + n // 16) * esz <= 150 * 1024, (prec, n, w, vpt)
+                    assert radix in (min(n, 16), 8) and vpt % radix == 0
     w = C.c_int()
-    assert b.lib.pst_column_variant_info(b.PST_FP32, 4096, 9, 1, C.byref(w), C.byref(w), C.byref(w)) \
-        == b.PST_ERR_INVALID
-    assert b.lib.pst_column_variant_info(b.PST_FP32, 3000, 0, 1, C.byref(w), C.byref(w), C.byref(w)) \
-        == b.PST_ERR_INVALID
+    assert b.lib.pst_column_variant_info(b.PST_FP32, 4096, 9, 1, C.byref(w), C.byref(w), C.byref(w),
+                                         C.byref(w)) == b.PST_ERR_INVALID
+    assert b.lib.pst_column_variant_info(b.PST_FP32, 3000, 0, 1, C.byref(w), C.byref(w), C.byref(w),
+                                         C.byref(w)) == b.PST_ERR_INVALID
     assert b.lib.pst_set_column_variant(None, 0) == b.PST_ERR_INVALID
+
+
+def test_row_variant_table_on_host(lib):
+    # NLS in-place row pass: one line per block from 4096 on (default, split,
+    # radix 8 split, radix 8 complex), row pairs below (default P, P/2, 2P)
+    from paper_1206_3215_amd import binding as b
+    assert b.row_variants(b.PST_FP64, 4096) == [(0, 16, 0, 16), (0, 16, 1, 16), (0, 8, 1, 8), (0, 8, 0, 8)]
+    assert b.row_variants(b.PST_FP32, 8192) == [(0, 32, 1, 16), (0, 16, 1, 16), (0, 8, 1, 8), (0, 8, 0, 8)]
+    assert b.row_variants(b.PST_FP32, 1024) == [(2, 16, 0, 16), (1, 16, 0, 16), (4, 16, 0, 16)]
+    assert b.row_variants(b.PST_FP64, 2048) == [(1, 16, 0, 16), (2, 16, 0, 16)]
+    for prec in (b.PST_FP32, b.PST_FP64):
+        for e in range(2, 14):
+            n = 1 << e
+            vs = b.row_variants(prec, n)
+            assert len(vs) >= 1
+            for pairs, vpt, split, radix in vs:
+                threads = n // vpt * (2 * pairs if pairs else 1)
+                assert threads <= 1024 and vpt % radix == 0, (prec, n, pairs, vpt)
+    assert b.lib.pst_set_row_variant(None, 0) == b.PST_ERR_INVALID

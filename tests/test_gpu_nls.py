@@ -14,13 +14,14 @@ pytestmark = pytest.mark.gpu
 TOL = {0: 1e-4, 1: 1e-11}
 
 
-def run_gpu(psi0, d, dt, g, nsteps, prec, chunk=None, diag=False, variant=0):
+def run_gpu(psi0, d, dt, g, nsteps, prec, chunk=None, diag=False, variant=0, row_variant=0):
     torch = need_gpu()
     from paper_1206_3215_amd import binding as b
     batch = psi0.shape[0] if psi0.ndim == 3 else 1
     ny, nx = psi0.shape[-2:]
     plan = b.Plan(nx, ny, b.PST_C2C, prec, batch)
     plan.set_column_variant(variant)
+    plan.set_row_variant(row_variant)
     psi = to_dev(psi0.reshape(batch, ny, nx), torch, plan.complex_dtype)
     diags = []
     chunk = chunk or nsteps
@@ -112,7 +113,7 @@ def oracle_4096_10():
     return psi0, ref
 
 
-@pytest.mark.parametrize("prec,variant", [(0, 0), (0, 1), (0, 2), (0, 3), (1, 0), (1, 1), (1, 2)])
+@pytest.mark.parametrize("prec,variant", [(0, v) for v in range(5)] + [(1, v) for v in range(6)])
 def test_headline_size_against_oracle_short(prec, variant, oracle_4096_10):
     # 4096^2 on [-5pi,5pi)^2, 10 steps, in every column variant (the
     # benchmark runs the one the autotuner picks).
@@ -122,15 +123,42 @@ def test_headline_size_against_oracle_short(prec, variant, oracle_4096_10):
     assert rel_err(got, ref) < TOL[prec]
 
 
-@pytest.mark.parametrize("prec,variant", [(0, 1), (1, 0), (1, 2)])
-def test_plane_wave_closed_form_8192(prec, variant):
+@pytest.mark.parametrize("prec,row", [(p, r) for p in (0, 1) for r in range(4)])
+def test_headline_size_row_variants(prec, row, oracle_4096_10):
+    # every row variant of the in-place row pass at 4096 (split exchange,
+    # radix 8), with the radix-8 column variant in FP64
+    d = inputs.PAPER_DOMAIN
+    psi0, ref = oracle_4096_10
+    got, _ = run_gpu(psi0, d, 1e-3, 1.0, 10, prec, variant=5 if prec else 0, row_variant=row)
+    assert rel_err(got, ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("n", [64, 1024, 2048])
+def test_pair_row_variants_bitwise_equal(prec, n):
+    # the row-pair pass in each pairs-per-block variant: same arithmetic, so
+    # bit-identical to the default, and within tolerance of the oracle
+    from paper_1206_3215_amd import binding as b
+    d = inputs.PAPER_DOMAIN
+    psi0 = np.stack([inputs.nls_gaussian(n, n // 2, d, seed=s) for s in range(3)])
+    base, _ = run_gpu(psi0, d, 1e-3, 1.0, 4, prec)
+    for r in range(1, len(b.row_variants(prec, n))):
+        got, _ = run_gpu(psi0, d, 1e-3, 1.0, 4, prec, row_variant=r)
+        assert np.array_equal(got, base), r
+    ref, _ = onls.run(psi0[1], d.lx, d.ly, 1e-3, 1.0, 4)
+    assert rel_err(base[1], ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec,variant,row", [(0, 1, 0), (0, 4, 2), (1, 0, 0), (1, 2, 1), (1, 4, 3), (1, 5, 2)])
+def test_plane_wave_closed_form_8192(prec, variant, row):
     # the largest compiled line length (32 values per thread and the split
-    # exchange in rows and in FP32 columns; FP64 columns in variants 0 and 2)
+    # exchange in rows and in FP32 columns; FP64 columns in variants 0 and 2;
+    # radix 8 and the wide split tiles)
     n, L, A, dt, steps = 8192, 10 * math.pi, 0.3, 1e-3, 20
     X, Y = inputs.grid(n, n, inputs.Domain(L, L, 0, 0))
     k = 2 * math.pi * np.array([-7, 4]) / L
     psi0 = A * np.exp(1j * (k[0] * X + k[1] * Y))
-    got, _ = run_gpu(psi0, inputs.Domain(L, L, 0, 0), dt, 1.0, steps, prec, variant=variant)
+    got, _ = run_gpu(psi0, inputs.Domain(L, L, 0, 0), dt, 1.0, steps, prec, variant=variant, row_variant=row)
     exact = psi0 * np.exp(-1j * (k @ k + A * A) * dt * steps)
     assert rel_err(got, exact) < TOL[prec]
 
