@@ -138,6 +138,21 @@ pst_status sg_start(pst_plan plan, const void* u0, const void* v0, void* u_prev,
 pst_status sg_step(pst_plan plan, void* u_prev, void* u_curr, const pst_sg_params* p,
                    int nsteps);
 
+/* sg_step for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same steps and results as sg_step, with the work arrays in a fixed
+ * 64 MiB device array of the library (one per GPU, held until the process
+ * ends) instead of the plan's workspace; calls no allocating routine.  The
+ * plan's device must be current.  Its three half spectra need
+ * 3 * batch * ny * (nx/2+1) complex values of the plan's precision (each
+ * array rounded up to 256 bytes): up to 2048 x 2048 FP32 or 1024 x 1024
+ * FP64 per field; PST_ERR_INVALID beyond 64 MiB.  Every call on one GPU
+ * shares that array: calls that overlap on a GPU (other streams, other
+ * threads) race; calls ordered on one stream do not.  Per-pass profiling
+ * events are not recorded. */
+pst_status sg_step_noalloc(pst_plan plan, void* u_prev, void* u_curr, const pst_sg_params* p,
+                           int nsteps);
+
 /* Navier-Stokes (Section "A Numerical Method for the 2D Navier-Stokes
  * Equation"): nsteps Crank-Nicolson steps, the Jacobian
  * J = psi_y omega_x - psi_x omega_y averaged between levels n and n+1 and

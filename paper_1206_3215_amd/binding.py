@@ -68,6 +68,7 @@ _SIGS = {
     "nls_step": [_vp, _vp, C.POINTER(NlsParams), C.c_int],
     "sg_start": [_vp, _vp, _vp, _vp, _vp, C.POINTER(SgParams)],
     "sg_step": [_vp, _vp, _vp, C.POINTER(SgParams), C.c_int],
+    "sg_step_noalloc": [_vp, _vp, _vp, C.POINTER(SgParams), C.c_int],
     "ns_step": [_vp, _vp, C.POINTER(NsParams), C.c_int, _vp],
     "conserved_quantities": [_vp, C.c_int, _vp, _vp, _vp, C.POINTER(C.c_double)],
     "pst_sync_status": [_vp, C.POINTER(C.c_int)],
@@ -223,6 +224,14 @@ class Plan:
         self._real_field(u_curr, "u_curr")
         p = SgParams(domain(d), dt)
         check(lib.sg_step(self.handle, _ptr(u_prev), _ptr(u_curr), C.byref(p), nsteps), "sg_step")
+
+    def sg_step_noalloc(self, u_prev, u_curr, d, dt: float, nsteps: int) -> None:
+        """sg_step with the library's fixed scratch array as workspace."""
+        self._need_kind(PST_R2C, "sg_step_noalloc")
+        self._real_field(u_prev, "u_prev")
+        self._real_field(u_curr, "u_curr")
+        p = SgParams(domain(d), dt)
+        check(lib.sg_step_noalloc(self.handle, _ptr(u_prev), _ptr(u_curr), C.byref(p), nsteps), "sg_step_noalloc")
 
     def ns_step(self, omega, d, dt: float, nu: float, nsteps: int, tol: float = 1e-10,
                 max_iter: int = 50, fixed_iters: int = 0, dev_iters=None) -> None:

@@ -71,6 +71,22 @@ void prof_begin(Plan* pl, int pass);
 void prof_end(Plan* pl);
 
 inline void* ws_at(Plan* pl, size_t off) { return static_cast<char*>(pl->ws) + off; }
+
+// Sine-Gordon steps (solvers.cpp) on work arrays the caller chooses: the
+// half spectra U, S and W, each [batch][ny][nx/2+1] complex of the plan's
+// precision.  sg_params_check validates without touching the workspace;
+// sg_work_bytes is the size of the three arrays (each 256-byte aligned) and
+// sg_work_at lays them out from base.
+struct SgWork {
+  void* U;
+  void* S;
+  void* W;
+};
+pst_status sg_params_check(Plan* pl, const pst_sg_params* p, const char* who);
+size_t sg_work_bytes(const Plan* pl);
+SgWork sg_work_at(const Plan* pl, void* base);
+pst_status sg_run_in(Plan* pl, const SgWork& w, FieldRef u_prev, FieldRef u_curr, const pst_sg_params* p,
+                     int nsteps, int* const* fstat, bool profile);
 inline int col_w(Plan* pl, int n) { return n == pl->ny ? pl->colvar : 0; }
 
 }  // namespace pst

@@ -187,11 +187,35 @@ pst_status conserved_quantities(pst_plan pl, pst_eq eq, const void* f0, const vo
   return PST_OK;
 }
 
-static pst_status sg_check(Plan* pl, const pst_sg_params* p, const char* who) {
+}  // extern "C"
+
+namespace pst {
+
+pst_status sg_params_check(Plan* pl, const pst_sg_params* p, const char* who) {
   TRY(need_kind(pl, PST_R2C, who));
   if (p == nullptr) return fail(PST_ERR_INVALID, "%s: params is NULL", who);
   TRY(check_domain(p->d));
   if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(PST_ERR_INVALID, "%s: dt must be finite and > 0", who);
+  return PST_OK;
+}
+
+size_t sg_work_bytes(const Plan* pl) {
+  const size_t a = ((size_t)pl->batch * pl->ny * (pl->nx / 2 + 1) * pl->csize + 255) & ~(size_t)255;
+  return 3 * a;
+}
+
+SgWork sg_work_at(const Plan* pl, void* base) {
+  const size_t a = sg_work_bytes(pl) / 3;
+  char* b = static_cast<char*>(base);
+  return SgWork{b, b + a, b + 2 * a};
+}
+
+}  // namespace pst
+
+extern "C" {
+
+static pst_status sg_check(Plan* pl, const pst_sg_params* p, const char* who) {
+  TRY(sg_params_check(pl, p, who));
   return ensure_workspace(pl);
 }
 
@@ -224,25 +248,30 @@ pst_status sg_start(pst_plan pl, const void* u0, const void* v0, void* u_prev, v
                    "sg start row");
 }
 
-// nsteps of the pl->batch field pairs (u_prev, u_curr); fstat as in nls_run.
-static pst_status sg_run(Plan* pl, FieldRef u_prev, FieldRef u_curr, const pst_sg_params* p, int nsteps,
-                         int* const* fstat = nullptr) {
+}  // extern "C"
+
+// nsteps of the pl->batch field pairs (u_prev, u_curr) in the work arrays w;
+// fstat as in nls_run; profile: bracket passes with events when the plan's
+// profiling is on.
+pst_status pst::sg_run_in(Plan* pl, const SgWork& w, FieldRef u_prev, FieldRef u_curr, const pst_sg_params* p,
+                          int nsteps, int* const* fstat, bool profile) {
   if (nsteps == 0) return PST_OK;
   const int nx = pl->nx, ny = pl->ny, B = pl->batch, lines = B * ny;
-  void* U = ws_at(pl, pl->off_spec);
-  void* S = ws_at(pl, pl->off_spec2);
-  void* W = ws_at(pl, pl->off_spec3);
+  void* U = w.U;
+  void* S = w.S;
+  void* W = w.W;
+  const bool prof = profile && pl->prof;
   const double sc = 0.5 / ((double)nx * ny), dt = p->dt;
   const double kx0 = 2 * M_PI / p->d.lx, ky0 = 2 * M_PI / p->d.ly;
   const int Wt = col_w(pl, ny);
   hipStream_t s = pl->stream;
   const FieldRef none;
   auto col = [&]() {
-    prof_begin(pl, PST_PASS_SG_COL);
+    if (prof) prof_begin(pl, PST_PASS_SG_COL);
     pst_status r = hip_check(sg_col(pl->P, ny, nx, B, U, S, W, pl->tw_y, kx0, ky0, 0.25 * dt * dt, 2.0, dt * dt, sc,
                                     Wt, s),
                              "sg column");
-    prof_end(pl);
+    if (prof) prof_end(pl);
     return r;
   };
   // u_curr holds u^n; u_prev's buffer holds the increment d^n during the call
@@ -250,10 +279,10 @@ static pst_status sg_run(Plan* pl, FieldRef u_prev, FieldRef u_curr, const pst_s
                 "sg entry row"));
   TRY(col());
   for (int i = 0; i < nsteps - 1; ++i) {
-    prof_begin(pl, PST_PASS_SG_ROW);
+    if (prof) prof_begin(pl, PST_PASS_SG_ROW);
     TRY(hip_check(sg_row(pl->P, 1, nx, lines, ny, W, u_curr, u_prev, 1.0, u_curr, u_prev, none, U, S, pl->tw_x, s),
                   "sg row"));
-    prof_end(pl);
+    if (prof) prof_end(pl);
     TRY(col());
   }
   // last step: u_curr <- u^N, u_prev <- u^{N-1} (the level it replaces)
@@ -264,6 +293,15 @@ static pst_status sg_run(Plan* pl, FieldRef u_prev, FieldRef u_curr, const pst_s
                           pl->tw_x, s, sr),
                    "sg final row");
 }
+
+// sg_run_in on the plan's workspace.
+static pst_status sg_run(Plan* pl, FieldRef u_prev, FieldRef u_curr, const pst_sg_params* p, int nsteps,
+                         int* const* fstat = nullptr) {
+  const SgWork w{ws_at(pl, pl->off_spec), ws_at(pl, pl->off_spec2), ws_at(pl, pl->off_spec3)};
+  return sg_run_in(pl, w, u_prev, u_curr, p, nsteps, fstat, true);
+}
+
+extern "C" {
 
 pst_status sg_step(pst_plan pl, void* u_prev, void* u_curr, const pst_sg_params* p, int nsteps) {
   TRY(sg_check(pl, p, "sg_step"));
