@@ -2,7 +2,7 @@
 precision, with the other workloads beside it.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp64|fp32] [--n N]
-                    [--no-cpu-baseline] [--serve COUNT] [--skip fp32,sg,ns,sweep]
+                    [--no-cpu-baseline] [--serve COUNT] [--skip fp32,sg,ns,sweep,ablation]
                     [--sweep] [--extra [nls]]
 
 Headline workload: a 4096^2 periodic grid on [-5pi,5pi)^2, psi0 = 0.5 exp(-r^2)
@@ -22,6 +22,8 @@ One JSON line on stdout carries:
   navier_stokes_uneven  4 x 1024^2 + 4 x 2048^2 FP32 through solve_batch;
   paper_sweep           the paper's Tables 2-4 workloads: the 4096^2 rows
                         and sine-Gordon 8192^2 (every grid with --sweep);
+  autotune_ablation     default against autotuned tiles, every equation,
+                        256^2-4096^2, FP64 and FP32;
   serving               the 512-request mix: p50/p99 latency, throughput,
                         against the plain one-request-at-a-time path;
   cpu_baseline          the FP64 oracle timed on the host's cores on a
@@ -49,7 +51,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 NLS_PASS_BYTES = 16            # read + write of one complex value
 SG_ROW_BYTES, SG_COL_BYTES = 20, 12
 NS_COL_BYTES, NS_ROW_BYTES = 32, 20
-SECTIONS = ("fp32", "sg", "ns", "sweep")
+SECTIONS = ("fp32", "sg", "ns", "sweep", "ablation")
 
 
 def kernel_source_hash(files=("fft_line.hpp", "kernels.hpp", "k_nls.hip", "pst_common.hpp")) -> str:
@@ -358,6 +360,54 @@ def bench_sweep(b, inputs, full: bool):
     return res
 
 
+def bench_ablation(b, inputs, sizes=(256, 512, 1024, 2048, 4096)):
+    """Autotuner ablation: grid-pt-steps/s of one field with the default
+    tiles (row and column variant 0) against the autotuned ones, for each
+    equation, size and precision.  NLS 40 steps of dt 1e-3; sine-Gordon 40
+    steps of dt 1e-3; Navier-Stokes (Taylor-Green, nu 0.1, dt 1.25e-3) 8
+    steps of exactly 3 fixed-point iterations, so both sides do the same
+    work."""
+    import torch
+    d = inputs.PAPER_DOMAIN
+    out = {}
+    for prec, pname in ((b.PST_FP64, "fp64"), (b.PST_FP32, "fp32")):
+        cdt = torch.complex128 if prec == b.PST_FP64 else torch.complex64
+        rdt = torch.float64 if prec == b.PST_FP64 else torch.float32
+        for eq in ("nls", "sg", "ns"):
+            for n in sizes:
+                rates = {}
+                for mode in ("default", "autotuned"):
+                    p = b.Plan(n, n, b.PST_C2C if eq == "nls" else b.PST_R2C, prec, 1)
+                    if mode == "autotuned":
+                        p.autotune(eq)
+                    if eq == "nls":
+                        f = torch.from_numpy(inputs.nls_gaussian(n, n, d, seed=0)).to("cuda", cdt).reshape(1, n, n)
+                        run = lambda k, p=p, f=f: p.nls_step(f, d, 1e-3, 1.0, k)
+                        k = 40
+                    elif eq == "sg":
+                        u = torch.from_numpy(inputs.sg_gaussian(n, n, d, seed=0)[0]).to("cuda", rdt).reshape(1, n, n)
+                        v = u.clone()
+                        run = lambda k, p=p, u=u, v=v: p.sg_step(u, v, d, 1e-3, k)
+                        k = 40
+                    else:
+                        w = torch.from_numpy(inputs.taylor_green(n, 0.0, 0.1)).to("cuda", rdt).reshape(1, n, n)
+                        run = lambda k, p=p, w=w: p.ns_step(w, inputs.NS_DOMAIN, 1.25e-3, 0.1, k, fixed_iters=3)
+                        k = 8
+                    run(2)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    run(k)
+                    torch.cuda.synchronize()
+                    rates[mode] = n * n * k / (time.perf_counter() - t0)
+                    if mode == "autotuned":
+                        rates["variants"] = list(p.variants())
+                    del p
+                rates["speedup"] = rates["autotuned"] / rates["default"]
+                out[f"{eq}_{n}_{pname}"] = rates
+    out["unit"] = "grid-pt-steps/s (NS: steps of 3 fixed-point iterations)"
+    return out
+
+
 def bench_serve(count: int):
     """Serving mix: Poisson arrivals, equation uniform over {NLS, SG, NS},
     n = 2^e with e uniform on 7..11, steps uniform on 100..2000, FP32.
@@ -480,6 +530,9 @@ def main():
     if "sweep" not in skip or args.sweep:
         out["paper_sweep"] = bench_sweep(b, inputs, full=args.sweep)
         progress("paper sweep done")
+    if "ablation" not in skip:
+        out["autotune_ablation"] = bench_ablation(b, inputs)
+        progress("autotuner ablation done")
     if args.serve > 0:
         out["serving"] = bench_serve(args.serve)
         progress("serving done")

@@ -48,6 +48,42 @@ bool col_variant_info(Prec p, int n, int var, bool single, int* w, int* vpt, int
 // exchange, radix.  False if not compiled.
 bool nls_row_variant_info(Prec p, int n, int var, int* pairs, int* vpt, int* split, int* radix);
 
+// ------------------------------------------------------- mixed radix ---
+// Stage list of the line FFT of a length n = 2^a 3^b 5^c that is not a
+// power of two (k_mixed.hip): radix r[s] of stage s, the product ns[s] of
+// the earlier radices, and the offset toff[s] of its (r-1) ns entries in the
+// length's twiddle table (entry (q-1) ns + k = exp(-2 pi i q k / (ns r))).
+struct MixedLine {
+  int n = 0, nst = 0;
+  int r[14] = {}, ns[14] = {}, toff[14] = {};
+};
+// Whether a mixed-radix line of length n fits the passes' LDS (two buffers
+// of n complex values: FP32 up to 9600, FP64 up to 4800).
+bool mixed_supported(Prec p, int n);
+// C2C rows (nlines contiguous lines) and columns ([field][n][ld], first
+// ncols columns), times scale; in may equal out.
+hipError_t mixed_row_c2c(Prec p, const MixedLine& ml, int nlines, const void* in, void* out, bool inv,
+                         double scale, const void* tw, hipStream_t s);
+hipError_t mixed_col_c2c(Prec p, const MixedLine& ml, int ncols, int ld, int nfields, const void* src, void* dst,
+                         bool inv, double scale, const void* tw, hipStream_t s);
+// Real rows of length n: forward to the n/2+1 half spectrum, inverse from it
+// (times scale).
+hipError_t mixed_row_r2c(Prec p, const MixedLine& ml, int nlines, const void* in, void* out, const void* tw,
+                         hipStream_t s);
+hipError_t mixed_row_c2r(Prec p, const MixedLine& ml, int nlines, const void* in, void* out, double scale,
+                         const void* tw, hipStream_t s);
+// NLS passes with nls_row / nls_col semantics on plain rows (no pair
+// layout); fields of ny rows of ml.n (row pass) or nx (column pass).
+hipError_t mixed_nls_row(Prec p, const MixedLine& ml, int nlines, int ny, FieldRef psi, int mode,
+                         double phase_coef, double scale, const void* tw, hipStream_t s, StatusRef st);
+hipError_t mixed_nls_col(Prec p, const MixedLine& ml, int nx, int nfields, FieldRef psi, const void* tw,
+                         const void* ex, const void* ey, hipStream_t s);
+// NLS diagnostics partials in nls_cq_row / nls_cq_col layout (spec: FFT_x
+// then FFT_y of psi in place), for nls_cq_finish.
+hipError_t mixed_nls_cq(Prec p, const MixedLine& mlx, const MixedLine& mly, int nfields, const void* psi,
+                        void* spec, double* row_part, double* col_part, const void* twx, const void* twy,
+                        double kx0, double ky0, hipStream_t s);
+
 // ----------------------------------------------------------------- FFT ---
 // Row pass over nlines contiguous complex lines of length n: out = FFT(in)
 // (inverse if inv), times scale.  in may equal out.

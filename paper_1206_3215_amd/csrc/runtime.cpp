@@ -35,7 +35,55 @@ pst_status hip_check(hipError_t e, const char* what) {
   return fail(PST_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-static bool pow2_in_range(int n) { return n >= 4 && n <= 8192 && (n & (n - 1)) == 0; }
+int size_class(int n) {
+  if (n < 4 || n > 8192) return 0;
+  if ((n & (n - 1)) == 0) return 1;
+  int m = n;
+  for (int f : {2, 3, 5})
+    while (m % f == 0) m /= f;
+  return m == 1 ? 2 : 0;
+}
+
+// Stage list of a mixed-radix line (layout in launch.hpp): radix-5 and
+// radix-3 stages first, then radix 8 while it divides, then a 4 or a 2.
+static MixedLine mixed_line(int n) {
+  MixedLine ml;
+  ml.n = n;
+  int m = n, ns = 1, off = 0;
+  auto push = [&](int r) {
+    ml.r[ml.nst] = r;
+    ml.ns[ml.nst] = ns;
+    ml.toff[ml.nst] = off;
+    if (ml.nst > 0) off += (r - 1) * ns;
+    ns *= r;
+    ++ml.nst;
+    m /= r;
+  };
+  while (m % 5 == 0) push(5);
+  while (m % 3 == 0) push(3);
+  while (m % 8 == 0) push(8);
+  if (m % 4 == 0) push(4);
+  if (m % 2 == 0) push(2);
+  return ml;
+}
+
+// Twiddle table of a mixed-radix line, in double precision.
+static std::vector<std::complex<double>> mixed_twiddles(const MixedLine& ml) {
+  size_t len = 1;
+  for (int s = 1; s < ml.nst; ++s) len = std::max(len, (size_t)ml.toff[s] + (size_t)(ml.r[s] - 1) * ml.ns[s]);
+  std::vector<std::complex<double>> tab(len);
+  for (int s = 1; s < ml.nst; ++s) {
+    const int r = ml.r[s], ns = ml.ns[s];
+    const long M = (long)ns * r;
+    for (int q = 1; q < r; ++q)
+      for (int k = 0; k < ns; ++k) {
+        const long mm = ((long)q * k) % M;
+        const double ang = -2.0 * M_PI * (double)mm / (double)M;
+        tab[ml.toff[s] + (q - 1) * ns + k] = {std::cos(ang), std::sin(ang)};
+      }
+  }
+  return tab;
+}
 
 // Twiddle table of the line FFT of length n (layout in fft_line.hpp: the
 // stages of the default radix, then those of radix 8 where compiled), in
@@ -127,7 +175,8 @@ pst_status upload_complex(Plan* pl, const std::vector<std::complex<double>>& h, 
 }
 
 double wavenumber(int m, int n, double length) {
-  const int mm = m < n / 2 ? m : m - n;
+  // m in {0..n/2-1, -n/2..-1} for even n, {0..(n-1)/2, -(n-1)/2..-1} for odd n
+  const int mm = m < (n + 1) / 2 ? m : m - n;
   return 2.0 * M_PI * (double)mm / length;
 }
 
@@ -222,10 +271,14 @@ pst_status fft2d_plan(int nx, int ny, pst_kind kind, pst_prec prec, int batch, v
                       pst_plan* out) {
   if (out == nullptr) return fail(PST_ERR_INVALID, "out is NULL");
   *out = nullptr;
-  if (!pow2_in_range(nx) || !pow2_in_range(ny))
-    return fail(PST_ERR_INVALID, "nx=%d, ny=%d: sizes must be powers of two in [4, 8192]", nx, ny);
+  if (!size_class(nx) || !size_class(ny))
+    return fail(PST_ERR_INVALID, "nx=%d, ny=%d: sizes must be 2^a 3^b 5^c in [4, 8192]", nx, ny);
   if (kind != PST_C2C && kind != PST_R2C) return fail(PST_ERR_INVALID, "unknown kind %d", (int)kind);
   if (prec != PST_FP32 && prec != PST_FP64) return fail(PST_ERR_INVALID, "unknown precision %d", (int)prec);
+  const bool mixed = size_class(nx) == 2 || size_class(ny) == 2;
+  if (mixed && (!mixed_supported(prec == PST_FP32 ? P32 : P64, nx) || !mixed_supported(prec == PST_FP32 ? P32 : P64, ny)))
+    return fail(PST_ERR_UNSUPPORTED, "nx=%d, ny=%d: lengths that are not powers of two are limited to %d (%s)", nx,
+                ny, prec == PST_FP32 ? 9600 : 4800, prec == PST_FP32 ? "FP32" : "FP64");
   if (batch < 1 || batch > (1 << 20)) return fail(PST_ERR_INVALID, "batch=%d out of range", batch);
   Plan* pl = new Plan();
   pl->nx = nx;
@@ -237,9 +290,19 @@ pst_status fft2d_plan(int nx, int ny, pst_kind kind, pst_prec prec, int batch, v
   pl->csize = prec == PST_FP32 ? 8 : 16;
   pl->rsize = prec == PST_FP32 ? 4 : 8;
   pl->P = prec == PST_FP32 ? P32 : P64;
+  pl->mixed = mixed;
   pst_status st = hip_check(hipGetDevice(&pl->device), "hipGetDevice");
-  if (st == PST_OK) st = upload_complex(pl, twiddles(nx), &pl->tw_x, true, 1.0);
-  if (st == PST_OK) st = upload_complex(pl, twiddles(ny), &pl->tw_y, true, 1.0);
+  if (mixed) {
+    // every pass of a plan with a non-power-of-two length runs the
+    // mixed-radix kernels, for both axes
+    pl->mlx = mixed_line(nx);
+    pl->mly = mixed_line(ny);
+    if (st == PST_OK) st = upload_complex(pl, mixed_twiddles(pl->mlx), &pl->tw_x, true, 1.0);
+    if (st == PST_OK) st = upload_complex(pl, mixed_twiddles(pl->mly), &pl->tw_y, true, 1.0);
+  } else {
+    if (st == PST_OK) st = upload_complex(pl, twiddles(nx), &pl->tw_x, true, 1.0);
+    if (st == PST_OK) st = upload_complex(pl, twiddles(ny), &pl->tw_y, true, 1.0);
+  }
   if (st == PST_OK) {
     void* p = nullptr;
     st = hip_check(hipMalloc(&p, 256 + (size_t)batch * 8 * sizeof(double)), "hipMalloc(status)");
@@ -300,6 +363,26 @@ pst_status fft2d_exec(pst_plan pl, const void* in, void* out, int sign) {
   const int nx = pl->nx, ny = pl->ny, B = pl->batch, h = nx / 2 + 1;
   const bool inv = sign == 1;
   const double sc = inv ? 1.0 / ((double)nx * ny) : 1.0;
+  if (pl->mixed) {
+    if (pl->kind == PST_C2C) {
+      st = hip_check(mixed_row_c2c(pl->P, pl->mlx, B * ny, in, out, inv, 1.0, pl->tw_x, pl->stream), "row pass");
+      if (st != PST_OK) return st;
+      return hip_check(mixed_col_c2c(pl->P, pl->mly, nx, nx, B, out, out, inv, sc, pl->tw_y, pl->stream),
+                       "column pass");
+    }
+    if (in == out) return fail(PST_ERR_INVALID, "R2C transforms cannot run in place");
+    if (!inv) {
+      st = hip_check(mixed_row_r2c(pl->P, pl->mlx, B * ny, in, out, pl->tw_x, pl->stream), "r2c row pass");
+      if (st != PST_OK) return st;
+      return hip_check(mixed_col_c2c(pl->P, pl->mly, h, h, B, out, out, false, 1.0, pl->tw_y, pl->stream),
+                       "column pass");
+    }
+    if ((st = ensure_workspace(pl)) != PST_OK) return st;
+    void* tmp = ws_at(pl, pl->off_spec);
+    st = hip_check(mixed_col_c2c(pl->P, pl->mly, h, h, B, in, tmp, true, 1.0, pl->tw_y, pl->stream), "column pass");
+    if (st != PST_OK) return st;
+    return hip_check(mixed_row_c2r(pl->P, pl->mlx, B * ny, tmp, out, sc, pl->tw_x, pl->stream), "c2r row pass");
+  }
   if (pl->kind == PST_C2C) {
     st = hip_check(fft_row_c2c(pl->P, nx, B * ny, in, out, inv, 1.0, pl->tw_x, pl->stream), "row pass");
     if (st != PST_OK) return st;
@@ -327,6 +410,10 @@ pst_status fft2d_exec(pst_plan pl, const void* in, void* out, int sign) {
 
 pst_status pst_set_column_variant(pst_plan pl, int variant) {
   if (pl == nullptr) return fail(PST_ERR_INVALID, "plan is NULL");
+  if (pl->mixed) {
+    if (variant != 0) return fail(PST_ERR_INVALID, "mixed-radix plans have only column variant 0");
+    return PST_OK;
+  }
   int w, v, sp, r;
   if (!col_variant_info(pl->P, pl->ny, variant, pl->kind == PST_C2C, &w, &v, &sp, &r))
     return fail(PST_ERR_INVALID, "column variant %d is not compiled for ny=%d", variant, pl->ny);
@@ -337,8 +424,8 @@ pst_status pst_set_column_variant(pst_plan pl, int variant) {
 pst_status pst_set_row_variant(pst_plan pl, int variant) {
   if (pl == nullptr) return fail(PST_ERR_INVALID, "plan is NULL");
   int p, v, sp, r;
-  if (pl->kind != PST_C2C) {
-    if (variant != 0) return fail(PST_ERR_INVALID, "R2C plans have only row variant 0");
+  if (pl->kind != PST_C2C || pl->mixed) {
+    if (variant != 0) return fail(PST_ERR_INVALID, "R2C and mixed-radix plans have only row variant 0");
   } else if (!nls_row_variant_info(pl->P, pl->nx, variant, &p, &v, &sp, &r)) {
     return fail(PST_ERR_INVALID, "row variant %d is not compiled for nx=%d", variant, pl->nx);
   }

@@ -28,6 +28,8 @@ struct pst_plan_s {
   hipStream_t stream = nullptr;
   int device = 0;
   size_t csize = 8, rsize = 4;  // bytes per complex / real element
+  bool mixed = false;           // nx or ny not a power of two: mixed-radix passes
+  pst::MixedLine mlx, mly;      // their stage lists (tw_x, tw_y then hold mixed-radix tables)
   int colvar = 0;               // column tile variant for length ny
   int rowvar = 0;               // row variant of the NLS in-place row pass (length nx)
   void* tw_x = nullptr;         // twiddles of the x lines (length nx)
@@ -63,6 +65,8 @@ pst_status upload_complex(Plan* pl, const std::vector<std::complex<double>>& h, 
                           double scale);
 pst_status check_domain(const pst_domain& d);
 pst_status check_field(const void* p, const char* name);
+// 1: a power of two in [4, 8192]; 2: another 2^a 3^b 5^c in [4, 8192]; 0: neither.
+int size_class(int n);
 pst_status ensure_workspace(Plan* pl);
 double wavenumber(int m, int n, double length);
 

@@ -85,6 +85,38 @@ static pst_status nls_run(Plan* pl, FieldRef psi, const pst_nls_params* p, int n
                           int* const* fstat = nullptr) {
   if (nsteps == 0) return PST_OK;
   TRY(nls_tables(pl, p));
+  if (pl->mixed) {
+    // the same sequence of passes on the mixed-radix kernels (plain rows)
+    const int nx = pl->nx, ny = pl->ny, B = pl->batch;
+    const double pc = p->g * p->dt / ((double)nx * nx);
+    const NlsTables& t = pl->nls;
+    hipStream_t s = pl->stream;
+    auto row = [&](int mode, double pc_, double scale, StatusRef sr) {
+      if (mode == 1) prof_begin(pl, PST_PASS_NLS_ROW);
+      pst_status r = hip_check(mixed_nls_row(pl->P, pl->mlx, B * ny, ny, psi, mode, pc_, scale, pl->tw_x, s, sr),
+                               "nls row");
+      if (mode == 1) prof_end(pl);
+      return r;
+    };
+    auto col = [&](const void* ex, const void* ey) {
+      prof_begin(pl, PST_PASS_NLS_COL);
+      pst_status r = hip_check(mixed_nls_col(pl->P, pl->mly, nx, B, psi, pl->tw_y, ex, ey, s), "nls column");
+      prof_end(pl);
+      return r;
+    };
+    TRY(row(0, 0.0, (double)nx, StatusRef()));
+    TRY(col(t.ex_half, t.ey_half));
+    for (int i = 1; i < nsteps; ++i) {
+      TRY(row(1, pc, 1.0, StatusRef()));
+      TRY(col(t.ex_full, t.ey_full));
+    }
+    TRY(row(1, pc, 1.0, StatusRef()));
+    TRY(col(t.ex_half, t.ey_half));
+    StatusRef sr;
+    sr.plan = pl->dstatus;
+    sr.field = fstat;
+    return row(2, 0.0, 1.0 / nx, sr);
+  }
   const int nx = pl->nx, ny = pl->ny, B = pl->batch, W = pl->colvar;
   const int lines = B * ny;
   const double pc = p->g * p->dt / ((double)nx * nx);
@@ -141,11 +173,19 @@ pst_status conserved_quantities(pst_plan pl, pst_eq eq, const void* f0, const vo
     void* spec = ws_at(pl, pl->off_spec);
     const double dxdy = (p->d.lx / nx) * (p->d.ly / ny);
     const double kin = 0.5 * p->d.lx * p->d.ly / ((double)nx * ny * (double)nx * ny);
-    TRY(hip_check(nls_cq_row(pl->P, nx, B * ny, f0, spec, rowp, pl->tw_x, s), "cq row"));
-    TRY(hip_check(nls_cq_col(pl->P, ny, nx, B, spec, colp, pl->tw_y, 2 * M_PI / p->d.lx,
-                             2 * M_PI / p->d.ly, 0, s),
-                  "cq column"));
+    if (pl->mixed) {
+      TRY(hip_check(mixed_nls_cq(pl->P, pl->mlx, pl->mly, B, f0, spec, rowp, colp, pl->tw_x, pl->tw_y,
+                                 2 * M_PI / p->d.lx, 2 * M_PI / p->d.ly, s),
+                    "cq passes"));
+    } else {
+      TRY(hip_check(nls_cq_row(pl->P, nx, B * ny, f0, spec, rowp, pl->tw_x, s), "cq row"));
+      TRY(hip_check(nls_cq_col(pl->P, ny, nx, B, spec, colp, pl->tw_y, 2 * M_PI / p->d.lx,
+                               2 * M_PI / p->d.ly, 0, s),
+                    "cq column"));
+    }
     TRY(hip_check(nls_cq_finish(B, ny, nx, rowp, colp, dxdy, kin, p->g, pl->dres, pl->dstatus, s), "cq finish"));
+  } else if (pl->mixed) {
+    return fail(PST_ERR_UNSUPPORTED, "conserved_quantities: sine-Gordon and Navier-Stokes need power-of-two sizes");
   } else if (eq == PST_SG) {
     TRY(need_kind(pl, PST_R2C, "conserved_quantities(SG)"));
     TRY(check_field(f1, "f1"));
@@ -193,6 +233,7 @@ namespace pst {
 
 pst_status sg_params_check(Plan* pl, const pst_sg_params* p, const char* who) {
   TRY(need_kind(pl, PST_R2C, who));
+  if (pl->mixed) return fail(PST_ERR_UNSUPPORTED, "%s: sine-Gordon needs power-of-two sizes", who);
   if (p == nullptr) return fail(PST_ERR_INVALID, "%s: params is NULL", who);
   TRY(check_domain(p->d));
   if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(PST_ERR_INVALID, "%s: dt must be finite and > 0", who);
@@ -315,6 +356,7 @@ pst_status sg_step(pst_plan pl, void* u_prev, void* u_curr, const pst_sg_params*
 
 static pst_status ns_check(Plan* pl, const pst_ns_params* p, int nsteps) {
   TRY(need_kind(pl, PST_R2C, "ns_step"));
+  if (pl->mixed) return fail(PST_ERR_UNSUPPORTED, "ns_step: Navier-Stokes needs power-of-two sizes");
   if (p == nullptr) return fail(PST_ERR_INVALID, "params is NULL");
   TRY(check_domain(p->d));
   if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(PST_ERR_INVALID, "dt must be finite and > 0");
@@ -572,6 +614,12 @@ extern "C" pst_status pst_autotune(pst_plan pl, pst_eq eq, int* chosen) {
   if (pl == nullptr) return fail(PST_ERR_INVALID, "plan is NULL");
   if (eq != PST_NLS && eq != PST_SG && eq != PST_NS) return fail(PST_ERR_INVALID, "unknown equation %d", (int)eq);
   TRY(need_kind(pl, eq == PST_NLS ? PST_C2C : PST_R2C, "pst_autotune"));
+  if (pl->mixed) {
+    // the mixed-radix passes have one configuration
+    pl->rowvar = pl->colvar = 0;
+    if (chosen) *chosen = 0;
+    return PST_OK;
+  }
   TRY(ensure_workspace(pl));
   const auto key = std::make_tuple((int)eq, (int)pl->prec, pl->nx, pl->ny);
   {
@@ -722,8 +770,10 @@ pst_status batch_plan(const pst_request& r, int slot, int cap, hipStream_t s, Ba
 
 pst_status check_request(const pst_request& r, int i) {
   if (r.eq != PST_NLS && r.eq != PST_SG && r.eq != PST_NS) return fail(PST_ERR_INVALID, "request %d: unknown equation", i);
-  if (r.nx < 4 || r.nx > 8192 || (r.nx & (r.nx - 1)) || r.ny < 4 || r.ny > 8192 || (r.ny & (r.ny - 1)))
-    return fail(PST_ERR_INVALID, "request %d: sizes must be powers of two in [4, 8192]", i);
+  if (!size_class(r.nx) || !size_class(r.ny))
+    return fail(PST_ERR_INVALID, "request %d: sizes must be 2^a 3^b 5^c in [4, 8192]", i);
+  if (r.eq != PST_NLS && (size_class(r.nx) != 1 || size_class(r.ny) != 1))
+    return fail(PST_ERR_UNSUPPORTED, "request %d: sine-Gordon and Navier-Stokes need power-of-two sizes", i);
   if (r.prec != PST_FP32 && r.prec != PST_FP64) return fail(PST_ERR_INVALID, "request %d: unknown precision", i);
   if (r.nsteps < 0) return fail(PST_ERR_INVALID, "request %d: nsteps < 0", i);
   if (r.params == nullptr) return fail(PST_ERR_INVALID, "request %d: params is NULL", i);

@@ -87,7 +87,7 @@ def gen_nls() -> None:
             series.append((k, onls.mass(psi, d.lx, d.ly), onls.energy(psi, d.lx, d.ly, 1.0)))
             log(f"nls step {k} ({time.time() - t0:.0f} s)")
     out = dict(spec)
-    out.update(take(psi, spec, ""))
+    out.update(take(psi, spec, "psi_"))
     out.update({"n": NLS_N, "dt": NLS_DT, "steps": NLS_STEPS, "g": 1.0, "seed": 0,
                 "series": np.array(series, dtype=np.float64)})
     np.savez_compressed(os.path.join(HERE, "ref_nls_4096_1000.npz"), **out)

@@ -40,9 +40,10 @@ def test_library_exports_every_declared_symbol(lib):
 def test_plan_rejects_bad_sizes_on_host(lib):
     from paper_1206_3215_amd import binding as b
     h = C.c_void_p()
-    for nx, ny, kind, prec, batch in [(3, 64, 0, 0, 1), (64, 12, 0, 0, 1), (2, 2, 0, 0, 1),
-                                      (16384, 64, 0, 0, 1), (64, 64, 7, 0, 1), (64, 64, 0, 5, 1),
-                                      (64, 64, 0, 0, 0)]:
+    # sizes must be 2^a 3^b 5^c in [4, 8192]: 3 is too small, 14 and 21 have a factor 7
+    for nx, ny, kind, prec, batch in [(3, 64, 0, 0, 1), (64, 14, 0, 0, 1), (21, 64, 0, 0, 1), (2, 2, 0, 0, 1),
+                                      (16384, 64, 0, 0, 1), (8000 * 2, 64, 0, 0, 1), (64, 64, 7, 0, 1),
+                                      (64, 64, 0, 5, 1), (64, 64, 0, 0, 0)]:
         st = b.lib.fft2d_plan(nx, ny, kind, prec, batch, None, C.byref(h))
         assert st == b.PST_ERR_INVALID, (nx, ny, kind, prec, batch)
         assert b.lib.pst_last_error().decode() != ""

@@ -43,6 +43,18 @@ def build_mix(prec):
     return mix
 
 
+def oracle_run(eq, f0, f1, prm, nsteps):
+    """The request's result computed by the FP64 oracle."""
+    from oracle import nls as onls, ns as ons, sg as osg
+    if eq == "nls":
+        return onls.run(f0, D_NLS.lx, D_NLS.ly, prm["dt"], 1.0, nsteps)[0], None
+    if eq == "sg":
+        a, c = osg.run(f0, f1, D_SG.lx, D_SG.ly, prm["dt"], nsteps)
+        return a, c
+    return ons.run(f0, D_NS.lx, D_NS.ly, prm["dt"], prm["nu"], nsteps, tol=prm.get("tol", 1e-10),
+                   max_iter=prm.get("max_iter", 50), fixed_iters=prm.get("fixed", 0))[0], None
+
+
 @pytest.mark.parametrize("prec", [1, 0])
 def test_mixed_batch_matches_single_runs(prec):
     torch = need_gpu()
@@ -67,6 +79,11 @@ def test_mixed_batch_matches_single_runs(prec):
         if ref1 is not None:
             assert rel_err(to_host(bb), ref1) < tol
         assert int(r["dev_status"].item()) == 0
+        # and against the oracle directly (SG: f0, f1 = u_prev, u_curr)
+        o0, o1 = oracle_run(eq, f0, f1, prm, steps)
+        assert rel_err(to_host(a), o0) < tol, ("oracle", eq, f0.shape, steps)
+        if o1 is not None:
+            assert rel_err(to_host(bb), o1) < tol, ("oracle", eq, f0.shape, steps)
 
 
 def test_uneven_ns_batch_bitwise_vs_alone():

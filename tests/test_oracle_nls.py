@@ -87,3 +87,14 @@ def test_second_order_in_time():
         errs.append(np.max(np.abs(psi - ref)))
     r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
     assert 3.6 < r1 < 4.4 and 3.6 < r2 < 4.4, errs
+
+
+@pytest.mark.parametrize("nx,ny", [(12, 20), (15, 9)])
+def test_plane_wave_exact_on_grids_that_are_not_powers_of_two(nx, ny):
+    # the scheme and the pin are the same on any grid: 2^a 3^b 5^c lengths,
+    # odd ones included, where the positive-frequency range differs
+    lx, ly, A, mx, my, dt, n = 5.0, 3.0, 0.6 - 0.3j, -4, 3, 0.02, 60
+    psi0 = plane_wave(nx, ny, lx, ly, mx, my, A, 1.0, 0.0)
+    got, _ = nls.run(psi0, lx, ly, dt, 1.0, n)
+    exact = plane_wave(nx, ny, lx, ly, mx, my, A, 1.0, dt * n)
+    assert np.max(np.abs(got - exact)) < 1e-12

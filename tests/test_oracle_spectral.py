@@ -22,7 +22,7 @@ def naive_dft2(f, sign=-1):
     return out
 
 
-@pytest.mark.parametrize("nx,ny", [(4, 4), (8, 8), (16, 16), (8, 4), (4, 16)])
+@pytest.mark.parametrize("nx,ny", [(4, 4), (8, 8), (16, 16), (8, 4), (4, 16), (6, 10), (15, 12), (5, 9), (20, 6)])
 def test_fft2_matches_naive_dft(nx, ny):
     rng = np.random.default_rng(nx * 100 + ny)
     f = rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx))
@@ -69,3 +69,12 @@ def test_quadrature_and_parseval_closed_forms():
     g = np.exp(-(X * X + Y * Y))
     assert abs(sp.integral(g * g, L, L) - math.pi / 2) < 1e-12
     assert abs(sp.grad_sq_integral(sp.fft2(g), L, L) - math.pi) < 1e-10
+
+
+@pytest.mark.parametrize("n", [5, 6, 9, 12, 15])
+def test_wavenumbers_of_lengths_that_are_not_powers_of_two(n):
+    # fftfreq order for any n: 0..ceil(n/2)-1, then the negative ones; an
+    # even n keeps -n/2 (the Nyquist mode), an odd n has none
+    m = [round(k / (2 * math.pi)) for k in sp.wavenumbers(n, 1.0)]
+    assert m == [j if j < (n + 1) // 2 else j - n for j in range(n)]
+    assert list(np.round(sp.rwavenumbers(n, 1.0) / (2 * math.pi))) == list(range(n // 2 + 1))
