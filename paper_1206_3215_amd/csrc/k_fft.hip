@@ -99,7 +99,7 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_row_r2c(
 
 template <typename T, int N>
 __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_row_c2r(
-    const cpx<T>* in, FieldRef out, int nlines, int lny, T scale, const cpx<T>* __restrict__ tw) {
+    const cpx<T>* in, FieldRef out, int nlines, int lny, T scale, const cpx<T>* __restrict__ tw, const int* skip) {
   using G = RowGeom<T, N>;
   constexpr int H = N / 2 + 1;
   extern __shared__ char smem[];
@@ -131,6 +131,8 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_row_c2r(
   }
   line_fft<N, true>(v, L, t, tw);
   const int ny = 1 << lny;
+  // (rows a and b lie in one field: ny is even)
+  if (skip != nullptr && va && skip[la >> lny]) return;
   gptr<T> oa = field<T>(out, la >> lny) + (size_t)(la & (ny - 1)) * N;
   gptr<T> ob = oa + N;
 #pragma unroll
@@ -216,7 +218,7 @@ hipError_t fft_row_r2c(Prec p, int n, int nlines, int ny, FieldRef in, void* out
 
 template <typename T>
 static hipError_t row_c2r(int n, int nlines, int ny, const void* in, FieldRef out, double scale,
-                          const void* tw, hipStream_t s) {
+                          const void* tw, hipStream_t s, const int* skip) {
   bool ok = dispatch_n(n, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
     using G = RowGeom<T, N>;
@@ -224,15 +226,15 @@ static hipError_t row_c2r(int n, int nlines, int ny, const void* in, FieldRef ou
     const int grid = (pairs + G::LPB - 1) / G::LPB;
     allow_lds((k_row_c2r<T, N>), G::LDS_BYTES);
     hipLaunchKernelGGL((k_row_c2r<T, N>), dim3(grid), dim3(G::THREADS), G::LDS_BYTES, s,
-                       (const cpx<T>*)in, out, nlines, ilog2c(ny), (T)scale, (const cpx<T>*)tw);
+                       (const cpx<T>*)in, out, nlines, ilog2c(ny), (T)scale, (const cpx<T>*)tw, skip);
   });
   return ok ? hipGetLastError() : hipErrorInvalidValue;
 }
 
 hipError_t fft_row_c2r(Prec p, int n, int nlines, int ny, const void* in, FieldRef out, double scale,
-                       const void* tw, hipStream_t s) {
-  return p == P32 ? row_c2r<float>(n, nlines, ny, in, out, scale, tw, s)
-                  : row_c2r<double>(n, nlines, ny, in, out, scale, tw, s);
+                       const void* tw, hipStream_t s, const int* skip) {
+  return p == P32 ? row_c2r<float>(n, nlines, ny, in, out, scale, tw, s, skip)
+                  : row_c2r<double>(n, nlines, ny, in, out, scale, tw, s, skip);
 }
 
 bool col_variant_info(Prec p, int n, int var, bool single, int* w, int* vpt, int* split, int* radix) {

@@ -123,7 +123,7 @@ struct NsColArgs {
 template <typename T, int N, int MODE, int WT>
 __global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_ns_col(const cpx<T>* NH, cpx<T>* WN, cpx<T>* Q, cpx<T>* DK,
                                                  cpx<T>* D, size_t dstride, cpx<T>* OUT, double* part,
-                                                 int tiles_per_field, const int* done, NsColArgs a,
+                                                 int tiles_per_field, const int* gate, NsColArgs a,
                                                  const cpx<T>* __restrict__ tw) {
   using G = ColGeom<T, N, WT>;
   constexpr int MY = N;  // column length (ny)
@@ -134,7 +134,9 @@ __global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_ns_col(const cpx
   const int c = threadIdx.x % WT, t = threadIdx.x / WT;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int field = tile / tiles_per_field;
-  if (MODE == NS_ITER && done[field]) return;  // uniform: a block is one field
+  // a field the gate marks (converged, or waiting for the host) is left
+  // alone; the decision is uniform, a block being one field
+  if (gate != nullptr && gate[field]) return;
   const int col = (tile % tiles_per_field) * WT + c;
   // Later iterations leave out the Nyquist column x: it lies beyond the 2/3
   // cut, so N is masked there and the update, the derivatives and the
@@ -320,14 +322,20 @@ __global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_ns_col(const cpx
 
 // Per field: residual r = dxdy/(nx ny) sum w |d^{k+1} - d^k|^2 against
 // tol_eff = max(tol, fp_floor * integral omega^2); updates done/iters.
-// mode 0: first iteration of a step; 1: later iterations; fixed > 0: run
-// exactly that many iterations.
+// first: the step's first iteration; fixed > 0: run exactly that many
+// iterations.  With park != NULL the iterations of a step were queued ahead
+// of time: a parked field (park[f] != 0) is skipped until the host resumes
+// it, a field that converges records its count in maxit, and one that has
+// not converged after the last queued iteration (last != 0) and has not
+// reached max_iter is parked (done is set so that later iterations skip
+// it, and park_step records the step of the chunk).
 __global__ __launch_bounds__(256) void k_ns_finish(int ncols, const double* part, double vol, double tol,
                                                    double fp_floor, int max_iter, int fixed, int first,
                                                    int* done, int* iters, int* iters_out, double* resid,
-                                                   int* status, int* const* fstat) {
+                                                   int* status, int* const* fstat, NsPark pk) {
   __shared__ double red[256];
   const int f = blockIdx.x, t = threadIdx.x;
+  if (pk.park != nullptr && pk.park[f]) return;
   if (!first && done[f]) return;
   double r = 0.0, z = 0.0;
   // after the first iteration the Nyquist column's residual term is zero and
@@ -362,6 +370,15 @@ __global__ __launch_bounds__(256) void k_ns_finish(int ncols, const double* part
     }
     done[f] = fin ? 1 : 0;
     if (iters_out) iters_out[f] = it;
+    if (pk.park != nullptr) {
+      if (fin) {
+        pk.maxit[f] = max(pk.maxit[f], it);
+      } else if (pk.last) {
+        pk.park[f] = 1;
+        pk.park_step[f] = pk.step;
+        done[f] = 1;
+      }
+    }
   }
 }
 
@@ -484,9 +501,20 @@ hipError_t ns_col(Prec p, int mode, int ny, int nfields, const NsPtrs& P, const 
 
 hipError_t ns_finish(int nfields, int ncols, const double* part, double vol, double tol, double fp_floor,
                      int max_iter, int fixed, int first, int* done, int* iters, int* iters_out, double* resid,
-                     int* status, int* const* fstat, hipStream_t s) {
+                     int* status, int* const* fstat, const NsPark& pk, hipStream_t s) {
   hipLaunchKernelGGL(k_ns_finish, dim3(nfields), dim3(256), 0, s, ncols, part, vol, tol, fp_floor, max_iter, fixed,
-                     first, done, iters, iters_out, resid, status, fstat);
+                     first, done, iters, iters_out, resid, status, fstat, pk);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_int(int* p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t fill_int(int* p, int n, int v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 

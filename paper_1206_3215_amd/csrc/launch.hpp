@@ -96,13 +96,14 @@ hipError_t fft_col_c2c(Prec p, int ny, int ncols, int ld, int nfields, const voi
                        bool inv, double scale, const void* tw, int W, hipStream_t s);
 
 // Real rows.  r2c: nlines real rows of length n -> half spectra (n/2+1).
-// c2r: half spectra -> real rows, times scale.  Rows are processed in
+// c2r: half spectra -> real rows, times scale (rows of a field f with
+// skip[f] != 0 are not stored; skip may be NULL).  Rows are processed in
 // pairs; nlines may be odd.
 // The real side is a FieldRef of fields with ny rows (ny a power of two).
 hipError_t fft_row_r2c(Prec p, int n, int nlines, int ny, FieldRef in, void* out, const void* tw,
                        hipStream_t s);
 hipError_t fft_row_c2r(Prec p, int n, int nlines, int ny, const void* in, FieldRef out, double scale,
-                       const void* tw, hipStream_t s);
+                       const void* tw, hipStream_t s, const int* skip = nullptr);
 
 // ----------------------------------------------------------------- NLS ---
 // mode 0: H = nx * FFT_x(psi); 1: H <- FFT_x(e^{-i c |iFFT_x H|^2} iFFT_x H);
@@ -174,13 +175,26 @@ struct NsScalars {
 hipError_t ns_row(Prec p, int nx, int nlines, int ny, const void* D, size_t dstride, void* NH, const int* done,
                   const void* tw, hipStream_t s);
 // Column pass, mode 0 entry / 1 first iteration / 2 later iteration / 3 exit.
-hipError_t ns_col(Prec p, int mode, int ny, int nfields, const NsPtrs& P, const NsScalars& S, const int* done,
+// Fields whose gate word is nonzero (gate may be NULL) are skipped.
+hipError_t ns_col(Prec p, int mode, int ny, int nfields, const NsPtrs& P, const NsScalars& S, const int* gate,
                   const void* tw, int Wt, hipStream_t s);
+// Iterations queued ahead of the host (see k_ns_finish): per-field park
+// flags, the step each parked field stopped in, the most iterations a
+// converged step took, whether this is the step's last queued iteration,
+// and the step's index in the chunk.  park == NULL: the host polls instead.
+struct NsPark {
+  int* park = nullptr;
+  int* park_step = nullptr;
+  int* maxit = nullptr;
+  int last = 0, step = 0;
+};
 // Convergence bookkeeping per field (see k_ns_finish); fstat, if not NULL,
 // holds a per-field pointer receiving that field's ST_ bits.
 hipError_t ns_finish(int nfields, int ncols, const double* part, double vol, double tol, double fp_floor,
                      int max_iter, int fixed, int first, int* done, int* iters, int* iters_out, double* resid,
-                     int* status, int* const* fstat, hipStream_t s);
+                     int* status, int* const* fstat, const NsPark& pk, hipStream_t s);
+// p[0..n) = v (a kernel, so that it may sit in a captured graph).
+hipError_t fill_int(int* p, int n, int v, hipStream_t s);
 // Diagnostics from omega's x-transform XH: energy and enstrophy.
 hipError_t ns_cq_col(Prec p, int ny, int nx, int nfields, const void* XH, double* part, double kx0, double ky0,
                      const void* tw, int Wt, hipStream_t s);

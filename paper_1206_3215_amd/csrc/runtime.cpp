@@ -225,7 +225,8 @@ size_t ws_layout(Plan* pl) {
     pl->off_hyb = take(4 * B * ny * h * pl->csize);
     pl->off_rowpart = take(B * ny * 4 * sizeof(double));
     pl->off_colpart = take(B * h * 4 * sizeof(double));
-    pl->off_nsstate = take(B * (2 * sizeof(int) + sizeof(double)) + 64);
+    // Navier-Stokes per-field state: done, iters, park, park_step, maxit, resid
+    pl->off_nsstate = take(B * (5 * sizeof(int) + sizeof(double)) + 64);
   }
   return off;
 }

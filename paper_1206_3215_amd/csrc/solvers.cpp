@@ -368,14 +368,18 @@ static pst_status ns_check(Plan* pl, const pst_ns_params* p, int nsteps) {
   return ensure_workspace(pl);
 }
 
-// nsteps of the pl->batch vorticity fields addressed by omega.
-// One NS call on a plan as a sequence of phases, so that the host can
-// interleave several plans' steps (solve_batch) or run them back to back
-// (ns_step).  A step: one row pass on w^n, the first column pass (forms q),
-// then the predicted number of further iterations, gated on the device by
-// the per-field convergence flags; the host then reads the flags (pinned
-// copy + event) and adds iterations until every field has converged or
-// max_iter is reached.  Fixed-K mode launches exactly K iterations.
+// Navier-Stokes steps of the pl->batch vorticity fields addressed by omega,
+// as a chunk: entry passes, the steps, exit passes.  Every step queues its
+// first iteration and then, gated per field on the device by the
+// convergence flags, a fixed number of further ones: exactly fixed_iters in
+// fixed-K mode, else the predicted count plus one (ns_guess: the most
+// iterations a step took recently).  A field still unconverged after the
+// last queued iteration of a step is parked: every later pass of the chunk
+// leaves it alone.  The host reads the flags once per chunk (an event on a
+// pinned copy); a parked field (rare) is then resumed on its own, with the
+// host checking after each iteration until its step converges or reaches
+// max_iter, and runs the rest of the chunk the same way.  Results do not
+// depend on the prediction, only the number of gated launches does.
 struct NsStepper {
   Plan* pl;
   FieldRef omega;
@@ -385,10 +389,10 @@ struct NsStepper {
   NsPtrs P;
   NsScalars S;
   int nx, ny, B, lines, h, Wt, fixed;
-  int *done, *iters;
+  int *done, *iters, *park, *park_step, *maxit;
   double* resid;
   double vol, fp_floor;
-  int step = 0, launched = 0;
+  int step = 0, target = 1, nsteps = 0;
 
   NsStepper(Plan* pl_, FieldRef omega_, const pst_ns_params* p_, int* dev_iters_, int* const* fstat_)
       : pl(pl_), omega(omega_), p(p_), dev_iters(dev_iters_), fstat(fstat_) {
@@ -415,15 +419,21 @@ struct NsStepper {
     S.nx = nx;
     S.kx_cut = (nx - 1) / 3;
     S.ky_cut = (ny - 1) / 3;
+    // per-field state, B ints each: done, iters, park, park_step, maxit
     done = static_cast<int*>(ws_at(pl, pl->off_nsstate));
     iters = done + B;
+    park = done + 2 * B;
+    park_step = done + 3 * B;
+    maxit = done + 4 * B;
     resid = reinterpret_cast<double*>(static_cast<char*>(ws_at(pl, pl->off_nsstate)) +
-                                      ((2 * B * sizeof(int) + 7) & ~(size_t)7));
+                                      ((5 * B * sizeof(int) + 7) & ~(size_t)7));
     vol = (p->d.lx / nx) * (p->d.ly / ny) / ((double)nx * ny);
     const double eps = pl->prec == PST_FP32 ? std::ldexp(1.0, -23) : 0.0;
     fp_floor = (16 * eps) * (16 * eps);
     fixed = p->fixed_iters;
+    target = fixed > 0 ? fixed : std::min(std::max(pl->ns_guess, 1) + 1, p->max_iter);
   }
+  bool adaptive() const { return fixed <= 0; }
   pst_status row(const int* gate) {
     prof_begin(pl, PST_PASS_NS_ROW);
     pst_status r = hip_check(ns_row(pl->P, nx, lines, ny, P.D, P.dstride, (void*)P.NH, gate, pl->tw_x, pl->stream),
@@ -431,91 +441,135 @@ struct NsStepper {
     prof_end(pl);
     return r;
   }
-  pst_status col(int mode) {
+  pst_status col(int mode, const int* gate) {
     if (mode == 1 || mode == 2) prof_begin(pl, PST_PASS_NS_COL);
-    pst_status r = hip_check(ns_col(pl->P, mode, ny, B, P, S, done, pl->tw_y, Wt, pl->stream), "ns column");
+    pst_status r = hip_check(ns_col(pl->P, mode, ny, B, P, S, gate, pl->tw_y, Wt, pl->stream), "ns column");
     if (mode == 1 || mode == 2) prof_end(pl);
     return r;
   }
-  pst_status finish(int first) {
+  pst_status finish(int first, int last) {
     int* iout = dev_iters ? dev_iters + (size_t)step * B : nullptr;
+    NsPark pk;
+    pk.park = park;
+    pk.park_step = park_step;
+    pk.maxit = maxit;
+    pk.last = last;
+    pk.step = step;
     return hip_check(ns_finish(B, h, P.part, vol, p->tol, fp_floor, p->max_iter, fixed, first, done, iters, iout,
-                               resid, pl->dstatus, fstat, pl->stream),
+                               resid, pl->dstatus, fstat, pk, pl->stream),
                      "ns finish");
   }
-  bool adaptive() const { return fixed <= 0; }
-  // entry: w^n = rfft2(omega), increment 0, derivatives of w^n
+  // -- the chunk, queued without host involvement (may be captured) -------
+  // entry: no field parked, w^n = rfft2(omega), increment 0, derivatives
   pst_status begin() {
-    if (adaptive()) {
-      // a cached batch plan can run a larger group than the one that first
-      // sized the flags' copy (every earlier copy has been waited for)
-      if (pl->ns_host_n < 2 * B) {
-        if (pl->ns_host != nullptr) {
-          TRY(hip_check(hipHostFree(pl->ns_host), "hipHostFree(ns flags)"));
-          pl->ns_host = nullptr;
-          pl->ns_host_n = 0;
-        }
-        TRY(hip_check(hipHostMalloc((void**)&pl->ns_host, 2 * B * sizeof(int), hipHostMallocDefault),
-                      "hipHostMalloc(ns flags)"));
-        pl->ns_host_n = 2 * B;
-      }
-      if (pl->ns_ev == nullptr)
-        TRY(hip_check(hipEventCreateWithFlags(&pl->ns_ev, hipEventDisableTiming), "hipEventCreate"));
-    }
+    TRY(hip_check(fill_int(park, 3 * B, 0, pl->stream), "clear ns state"));  // park, park_step, maxit
     TRY(hip_check(fft_row_r2c(pl->P, nx, lines, ny, omega, (void*)P.NH, pl->tw_x, pl->stream), "ns entry row"));
-    return col(0);
+    return col(0, nullptr);
   }
-  pst_status iterate() {
-    TRY(row(done));
-    TRY(col(2));
-    TRY(finish(0));
-    ++launched;
-    return PST_OK;
-  }
-  // queue a step's first iteration and its predicted further ones; in
-  // adaptive mode also the flags' copy to the host
-  pst_status start_step() {
-    TRY(row(nullptr));
-    TRY(col(1));
-    TRY(finish(1));
-    launched = 1;
-    const int target = fixed > 0 ? fixed : std::min(std::max(pl->ns_guess, 1), p->max_iter);
-    while (launched < target) TRY(iterate());
-    return adaptive() ? request_flags() : PST_OK;
-  }
-  pst_status request_flags() {
-    TRY(hip_check(hipMemcpyAsync(pl->ns_host, done, 2 * B * sizeof(int), hipMemcpyDeviceToHost, pl->stream),
-                  "read ns flags"));
-    return hip_check(hipEventRecord(pl->ns_ev, pl->stream), "hipEventRecord");
-  }
-  // adaptive mode: wait for the flags; *complete is set when the step has
-  // converged everywhere (or hit max_iter), otherwise one more iteration and
-  // the next flags copy are queued
-  pst_status poll(bool* complete) {
-    TRY(hip_check(hipEventSynchronize(pl->ns_ev), "hipEventSynchronize"));
-    bool all = true;
-    int most = 0;
-    for (int f = 0; f < B; ++f) {
-      all = all && pl->ns_host[f] != 0;
-      most = std::max(most, pl->ns_host[B + f]);
+  // one step: the first iteration and target - 1 gated ones; in adaptive
+  // mode the last of them parks an unconverged field
+  pst_status queue_step() {
+    TRY(row(park));
+    TRY(col(1, park));
+    TRY(finish(1, adaptive() && target == 1));
+    for (int i = 2; i <= target; ++i) {
+      TRY(row(done));
+      TRY(col(2, done));
+      TRY(finish(0, adaptive() && i == target));
     }
-    *complete = all || launched >= p->max_iter;
-    if (*complete) {
-      pl->ns_guess = std::max(1, most);
-      return PST_OK;
-    }
-    TRY(iterate());
-    return request_flags();
-  }
-  pst_status end_step() {
     ++step;
     return PST_OK;
   }
-  // exit: omega = irfft2(w^n + d)
-  pst_status end() {
-    TRY(col(3));
-    return hip_check(fft_row_c2r(pl->P, nx, lines, ny, P.OUT, omega, 1.0 / ((double)nx * ny), pl->tw_x, pl->stream),
-                     "ns exit row");
+  // exit: omega = irfft2(w^n + d) for the fields not parked
+  pst_status queue_exit() {
+    TRY(col(3, park));
+    return hip_check(
+        fft_row_c2r(pl->P, nx, lines, ny, P.OUT, omega, 1.0 / ((double)nx * ny), pl->tw_x, pl->stream, park),
+        "ns exit row");
+  }
+  pst_status queue_chunk(int k) {
+    nsteps = k;
+    step = 0;
+    TRY(begin());
+    for (int i = 0; i < k; ++i) TRY(queue_step());
+    return queue_exit();
+  }
+  // -- host side ------------------------------------------------------------
+  pst_status ensure_host(int ints) {
+    if (pl->ns_host_n < ints) {
+      if (pl->ns_host != nullptr) {
+        TRY(hip_check(hipStreamSynchronize(pl->stream), "hipStreamSynchronize"));
+        TRY(hip_check(hipHostFree(pl->ns_host), "hipHostFree(ns flags)"));
+        pl->ns_host = nullptr;
+        pl->ns_host_n = 0;
+      }
+      TRY(hip_check(hipHostMalloc((void**)&pl->ns_host, ints * sizeof(int), hipHostMallocDefault),
+                    "hipHostMalloc(ns flags)"));
+      pl->ns_host_n = ints;
+    }
+    if (pl->ns_ev == nullptr)
+      TRY(hip_check(hipEventCreateWithFlags(&pl->ns_ev, hipEventDisableTiming), "hipEventCreate"));
+    return PST_OK;
+  }
+  // copy iters, park, park_step, maxit (contiguous) to the host behind an event
+  pst_status request_flags() {
+    TRY(hip_check(hipMemcpyAsync(pl->ns_host, iters, 4 * B * sizeof(int), hipMemcpyDeviceToHost, pl->stream),
+                  "read ns flags"));
+    return hip_check(hipEventRecord(pl->ns_ev, pl->stream), "hipEventRecord");
+  }
+  // wait for the chunk's flags, update the prediction, resume parked fields
+  pst_status complete_chunk() {
+    TRY(hip_check(hipEventSynchronize(pl->ns_ev), "hipEventSynchronize"));
+    std::vector<int> hostv(pl->ns_host, pl->ns_host + 4 * B);
+    const int* h_iters = hostv.data();
+    const int* h_park = h_iters + B;
+    const int* h_pstep = h_iters + 2 * B;
+    const int* h_maxit = h_iters + 3 * B;
+    int most = 0;
+    for (int f = 0; f < B; ++f) most = std::max(most, h_maxit[f]);
+    for (int f = 0; f < B; ++f)
+      if (h_park[f]) TRY(resume(f, h_pstep[f], h_iters[f], &most));
+    if (most > 0) pl->ns_guess = most;
+    return PST_OK;
+  }
+  // field f stopped in step s of the chunk after `it` iterations: finish that
+  // step and the rest of the chunk with the others gated off, checking the
+  // convergence flags on the host after each iteration
+  pst_status resume(int f, int s, int it, int* most) {
+    TRY(hip_check(fill_int(park, B, 1, pl->stream), "gate ns fields"));
+    TRY(hip_check(fill_int(park + f, 1, 0, pl->stream), "gate ns fields"));
+    TRY(hip_check(fill_int(done, B, 1, pl->stream), "gate ns fields"));
+    TRY(hip_check(fill_int(done + f, 1, 0, pl->stream), "gate ns fields"));
+    step = s;
+    int launched = it;
+    // iterate (an unconverged field first iterates, then checks) until
+    // done[f] or max_iter
+    auto converge = [&](bool iterate_first) -> pst_status {
+      for (bool check = !iterate_first;; check = true) {
+        if (check) {
+          TRY(hip_check(hipMemcpyAsync(pl->ns_host, done + f, sizeof(int), hipMemcpyDeviceToHost, pl->stream),
+                        "read ns flag"));
+          TRY(hip_check(hipEventRecord(pl->ns_ev, pl->stream), "hipEventRecord"));
+          TRY(hip_check(hipEventSynchronize(pl->ns_ev), "hipEventSynchronize"));
+          if (pl->ns_host[0] != 0 || launched >= p->max_iter) break;
+        }
+        TRY(row(done));
+        TRY(col(2, done));
+        TRY(finish(0, 0));
+        ++launched;
+      }
+      *most = std::max(*most, launched);
+      return PST_OK;
+    };
+    TRY(converge(true));
+    for (++step; step < nsteps; ++step) {
+      TRY(row(park));
+      TRY(col(1, park));
+      TRY(finish(1, 0));
+      launched = 1;
+      TRY(converge(false));
+    }
+    return queue_exit();
   }
 };
 
@@ -523,16 +577,11 @@ static pst_status ns_run(Plan* pl, FieldRef omega, const pst_ns_params* p, int n
                          int* const* fstat = nullptr) {
   if (nsteps == 0) return PST_OK;
   NsStepper st(pl, omega, p, dev_iters, fstat);
-  TRY(st.begin());
-  for (int k = 0; k < nsteps; ++k) {
-    TRY(st.start_step());
-    if (st.adaptive()) {
-      bool complete = false;
-      while (!complete) TRY(st.poll(&complete));
-    }
-    TRY(st.end_step());
-  }
-  return st.end();
+  if (st.adaptive()) TRY(st.ensure_host(4 * pl->batch));
+  TRY(st.queue_chunk(nsteps));
+  if (!st.adaptive()) return PST_OK;
+  TRY(st.request_flags());
+  return st.complete_chunk();
 }
 
 pst_status ns_step(pst_plan pl, void* omega, const pst_ns_params* p, int nsteps, int* dev_iters) {
@@ -803,29 +852,12 @@ __global__ void k_scatter_status(const int* fst, int* const* dst, int n) {
 
 }  // namespace
 
-// One chunk of a group: every field advances by k steps.
-static pst_status run_chunk(BatchPlan& bp, int eq, const void* params, int nf, int k, bool capture,
-                            const std::vector<uintptr_t>& key) {
+// Launch a chunk's sequence on the batch plan's stream, or capture it into a
+// graph on the second occurrence of its key and replay it from the third.
+template <class L>
+static pst_status launch_or_replay(BatchPlan& bp, bool capture, const std::vector<uintptr_t>& key, L&& launch) {
   Plan* pl = bp.pl;
-  const int cap = pl->batch;
-  pl->batch = nf;  // the chunk's field count; restored on every return
-  struct Restore {
-    Plan* pl;
-    int cap;
-    ~Restore() { pl->batch = cap; }
-  } restore{pl, cap};
-  FieldRef f0, f1;
-  f0.table = bp.dtab;
-  f1.table = bp.dtab + cap;
   pst_status st = PST_OK;
-  int* const* fst = reinterpret_cast<int* const*>(bp.dtab + 2 * cap);
-  // tables are uploaded before any capture (a synchronous copy may not be captured)
-  if (eq == PST_NLS) TRY(nls_tables(pl, static_cast<const pst_nls_params*>(params)));
-  auto launch = [&]() -> pst_status {
-    if (eq == PST_NLS) return nls_run(pl, f0, static_cast<const pst_nls_params*>(params), k, fst);
-    if (eq == PST_SG) return sg_run(pl, f0, f1, static_cast<const pst_sg_params*>(params), k, fst);
-    return ns_run(pl, f0, static_cast<const pst_ns_params*>(params), k, nullptr, fst);
-  };
   auto g = bp.graphs.end();
   if (capture) {
     g = bp.graphs.find(key);
@@ -859,6 +891,30 @@ static pst_status run_chunk(BatchPlan& bp, int eq, const void* params, int nf, i
     if (st == PST_OK) st = hip_check(hipGraphLaunch(g->second, pl->stream), "graph launch");
   }
   return st;
+}
+
+// One chunk of a fixed-schedule group: every field advances by k steps.
+static pst_status run_chunk(BatchPlan& bp, int eq, const void* params, int nf, int k, bool capture,
+                            const std::vector<uintptr_t>& key) {
+  Plan* pl = bp.pl;
+  const int cap = pl->batch;
+  pl->batch = nf;  // the chunk's field count; restored on every return
+  struct Restore {
+    Plan* pl;
+    int cap;
+    ~Restore() { pl->batch = cap; }
+  } restore{pl, cap};
+  FieldRef f0, f1;
+  f0.table = bp.dtab;
+  f1.table = bp.dtab + cap;
+  int* const* fst = reinterpret_cast<int* const*>(bp.dtab + 2 * cap);
+  // tables are uploaded before any capture (a synchronous copy may not be captured)
+  if (eq == PST_NLS) TRY(nls_tables(pl, static_cast<const pst_nls_params*>(params)));
+  return launch_or_replay(bp, capture, key, [&]() -> pst_status {
+    if (eq == PST_NLS) return nls_run(pl, f0, static_cast<const pst_nls_params*>(params), k, fst);
+    if (eq == PST_SG) return sg_run(pl, f0, f1, static_cast<const pst_sg_params*>(params), k, fst);
+    return ns_run(pl, f0, static_cast<const pst_ns_params*>(params), k, nullptr, fst);
+  });
 }
 
 extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stream) {
@@ -981,12 +1037,22 @@ extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stre
     bp->used = true;
     return PST_OK;
   };
+  // the captured launches carry the parameters (time step, domain,
+  // coefficients) as kernel arguments: a graph is replayed only for the same
+  // parameter bytes
+  auto add_params = [&](size_t ji, std::vector<uintptr_t>* key) {
+    const std::vector<unsigned char>& pk = gkeys[jobs[ji].gi];
+    for (size_t b = 0; b < pk.size(); b += sizeof(uintptr_t)) {
+      uintptr_t w = 0;
+      memcpy(&w, pk.data() + b, std::min(sizeof(uintptr_t), pk.size() - b));
+      key->push_back(w);
+    }
+  };
   // fixed-schedule group: chunk after chunk, each a graph replay once seen
   auto run_fixed = [&](size_t ji) -> pst_status {
     const std::vector<int>& g = groups[jobs[ji].gi];
     BatchPlan* bp = jobs[ji].bp;
     const pst_request& r0 = reqs[g[0]];
-    const std::vector<unsigned char>& pk = gkeys[jobs[ji].gi];
     std::vector<int> left(g.size()), act;
     for (size_t j = 0; j < g.size(); ++j) left[j] = reqs[g[j]].nsteps;
     for (int k; (k = next_chunk(left, &act)) > 0;) {
@@ -994,24 +1060,17 @@ extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stre
       TRY(upload_table(ji, act, &key));
       key.push_back((uintptr_t)k);
       key.push_back((uintptr_t)act.size());
-      // the captured launches carry the parameters (time step, domain,
-      // coefficients) as kernel arguments: a graph is replayed only for the
-      // same parameter bytes
-      for (size_t b = 0; b < pk.size(); b += sizeof(uintptr_t)) {
-        uintptr_t w = 0;
-        memcpy(&w, pk.data() + b, std::min(sizeof(uintptr_t), pk.size() - b));
-        key.push_back(w);
-      }
+      add_params(ji, &key);
       TRY(run_chunk(*bp, r0.eq, r0.params, (int)act.size(), k, true, key));
       for (int a : act) left[a] -= k;
     }
     return close_group(ji);
   };
-  // Fixed-schedule groups first: their launches are asynchronous.  Adaptive
-  // NS groups then advance in lockstep, one step of every group at a time:
-  // each group's step is queued on its stream before the host waits for the
-  // first group's convergence flags, so the groups' host round trips and
-  // device work overlap.
+  // Fixed-schedule groups first: their launches are asynchronous.  Then the
+  // adaptive NS groups, chunk by chunk: a whole chunk of every open group is
+  // queued (captured into a graph once its schedule repeats), and only then
+  // does the host read each group's flags, once per chunk, resuming the rare
+  // field that needed more iterations than were queued.
   std::vector<size_t> adaptive;
   for (size_t ji = 0; ji < jobs.size() && result == PST_OK; ++ji) {
     if (jobs[ji].adaptive) adaptive.push_back(ji);
@@ -1020,7 +1079,7 @@ extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stre
   struct NsGroup {
     size_t ji;
     std::vector<int> left, act;
-    int k = 0, kdone = 0, cap = 0;
+    int k = 0, cap = 0;
     bool in_chunk = false, closed = false;
     std::unique_ptr<NsStepper> st;
   };
@@ -1035,40 +1094,42 @@ extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stre
   }
   for (bool busy = true; busy && result == PST_OK;) {
     busy = false;
-    for (NsGroup& q : ns) {  // queue one step of every open group
-      if (q.closed || result != PST_OK) continue;
+    for (NsGroup& q : ns) {  // queue a chunk of every open group
+      if (q.closed || q.in_chunk || result != PST_OK) continue;
       BatchPlan* bp = jobs[q.ji].bp;
       const pst_request& r0 = reqs[groups[jobs[q.ji].gi][0]];
-      if (!q.in_chunk) {
-        q.k = next_chunk(q.left, &q.act);
-        if (q.k == 0) {
-          q.closed = true;
-          result = close_group(q.ji);
-          continue;
-        }
-        if ((result = upload_table(q.ji, q.act, nullptr)) != PST_OK) break;
-        bp->pl->batch = (int)q.act.size();  // the chunk's field count, restored at its end
-        FieldRef f0;
-        f0.table = bp->dtab;
-        q.st.reset(new NsStepper(bp->pl, f0, static_cast<const pst_ns_params*>(r0.params), nullptr,
-                                 reinterpret_cast<int* const*>(bp->dtab + 2 * q.cap)));
-        q.in_chunk = true;
-        q.kdone = 0;
-        if ((result = q.st->begin()) != PST_OK) break;
+      q.k = next_chunk(q.left, &q.act);
+      if (q.k == 0) {
+        q.closed = true;
+        result = close_group(q.ji);
+        continue;
       }
+      std::vector<uintptr_t> key;
+      if ((result = upload_table(q.ji, q.act, &key)) != PST_OK) break;
+      bp->pl->batch = (int)q.act.size();  // the chunk's field count, restored when it completes
+      FieldRef f0;
+      f0.table = bp->dtab;
+      q.st.reset(new NsStepper(bp->pl, f0, static_cast<const pst_ns_params*>(r0.params), nullptr,
+                               reinterpret_cast<int* const*>(bp->dtab + 2 * q.cap)));
+      if ((result = q.st->ensure_host(4 * q.cap)) != PST_OK) break;
+      key.push_back((uintptr_t)q.k);
+      key.push_back((uintptr_t)q.act.size());
+      key.push_back((uintptr_t)q.st->target);
+      add_params(q.ji, &key);
+      NsStepper* stp = q.st.get();
+      const int k = q.k;
+      result = launch_or_replay(*bp, true, key, [&]() -> pst_status { return stp->queue_chunk(k); });
+      if (result == PST_OK) result = q.st->request_flags();
+      q.in_chunk = true;
       busy = true;
-      if ((result = q.st->start_step()) != PST_OK) break;
     }
-    for (NsGroup& q : ns) {  // wait for each, adding iterations where needed
+    for (NsGroup& q : ns) {  // wait for each chunk's flags
       if (!q.in_chunk || result != PST_OK) continue;
-      for (bool complete = false; !complete && result == PST_OK;) result = q.st->poll(&complete);
-      if (result == PST_OK) result = q.st->end_step();
-      if (result == PST_OK && ++q.kdone == q.k) {
-        result = q.st->end();
-        jobs[q.ji].bp->pl->batch = q.cap;
-        for (int a : q.act) q.left[a] -= q.k;
-        q.in_chunk = false;
-      }
+      result = q.st->complete_chunk();
+      jobs[q.ji].bp->pl->batch = q.cap;
+      for (int a : q.act) q.left[a] -= q.k;
+      q.in_chunk = false;
+      busy = true;
     }
   }
   for (NsGroup& q : ns) jobs[q.ji].bp->pl->batch = q.cap;  // also after an error

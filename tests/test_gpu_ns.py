@@ -154,3 +154,41 @@ def test_batch_member_bitwise_equal_alone():
     got, _, _, _ = gpu_ns(w0, D1, 1e-3, 1e-3, 5, 0, tol=1e-10)
     alone, _, _, _ = gpu_ns(w0[2:3], D1, 1e-3, 1e-3, 5, 0, tol=1e-10)
     assert np.array_equal(got[2], alone[0])
+
+
+def test_parked_field_resumes_and_matches_oracle():
+    # Iterations are queued ahead of the host (the predicted count plus one);
+    # a field that needs more is parked and resumed by the host.  Here one
+    # field needs 6 iterations per step and the others fewer: the first call
+    # (prediction 3) parks the hard field on its first step while the others
+    # finish the chunk; the second call on the same plan (prediction 6)
+    # parks nothing.  Every field and every step's iteration count must
+    # match the oracle's adaptive run.
+    hard = inputs.ns_random_phase(64, seed=3)
+    easy = [0.05 * inputs.ns_random_phase(64, seed=s) for s in (4, 5)]
+    w0 = np.stack([easy[0], hard, easy[1]])
+    torch = need_gpu()
+    from paper_1206_3215_amd import binding as b
+    plan = b.Plan(64, 64, b.PST_R2C, b.PST_FP64, 3)
+    W = to_dev(w0, torch, torch.float64)
+    for call in range(2):
+        its = torch.zeros(5 * 3, dtype=torch.int32, device="cuda")
+        before = to_host(W).copy()
+        plan.ns_step(W, D1, 1e-3, 1e-3, 5, tol=1e-10, dev_iters=its)
+        assert plan.sync_status() == b.PST_OK
+        got, its = to_host(W), to_host(its).reshape(5, 3)
+        for i in range(3):
+            ref, rits, ok = ons.run(before[i], 1.0, 1.0, 1e-3, 1e-3, 5, tol=1e-10)
+            assert ok and list(its[:, i]) == rits, (call, i, its[:, i], rits)
+            assert rel_err(got[i], ref) < TOL[1], (call, i)
+        assert max(its[:, 1]) > 4 > max(its[:, 0])       # the hard field outran the first prediction
+
+
+def test_fixed_iterations_need_no_host_wait_and_match_adaptive_counts():
+    # fixed-K mode queues exactly K iterations per step (no parking); with K
+    # equal to the adaptive count the two agree to rounding
+    w0 = inputs.ns_random_phase(64, seed=3)
+    fixed, _, st, _ = gpu_ns(w0, D1, 1e-3, 1e-3, 4, 1, fixed=6)
+    adapt, its, _, _ = gpu_ns(w0, D1, 1e-3, 1e-3, 4, 1, tol=1e-10, want_iters=True)
+    assert st == 0 and list(its[:, 0]) == [6, 6, 6, 6]
+    assert rel_err(fixed[0], adapt[0]) < 1e-13
