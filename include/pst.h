@@ -249,7 +249,9 @@ const char* pst_version(void);
  * threads and 150 KB of LDS, 16 values of a line per thread, complex values
  * exchanged through LDS between stages, radix 16.  For two-line passes
  * (sine-Gordon, Navier-Stokes, real transforms) and for single-field passes
- * shorter than 4096, variant 1 is half of variant 0's W.  Single-field
+ * shorter than 4096, variant 1 is half of variant 0's W; two-line passes of
+ * lines of 512 and more add 2 and 3, a quarter and an eighth of it (those
+ * that are at least 1).  Single-field
  * column passes (NLS steps and C2C transforms) of lines of 4096 and more add,
  * in FP32:
  *   1: the same W, 32 values per thread, real and imaginary parts exchanged

@@ -206,6 +206,9 @@ bool dispatch_nls_row(int var, F&& f) {
 
 // Calls f(IntC<W>) for variant `var` of a two-line column pass.
 template <typename T, int N, class F>
+// Lines of 512 and more add a quarter and an eighth of variant 0's W (as
+// far as they are >= 1): a batch of small fields then runs several blocks
+// per CU instead of one.
 bool dispatch_w(int var, F&& f) {
   using CT = ColTiles<T, N>;
   if (var == 0) {
@@ -215,6 +218,18 @@ bool dispatch_w(int var, F&& f) {
   if (var == 1) {
     f(std::integral_constant<int, CT::WALT>{});
     return true;
+  }
+  if constexpr (N >= 512 && CT::WMAX >= 4) {
+    if (var == 2) {
+      f(std::integral_constant<int, CT::WMAX / 4>{});
+      return true;
+    }
+  }
+  if constexpr (N >= 512 && CT::WMAX >= 8) {
+    if (var == 3) {
+      f(std::integral_constant<int, CT::WMAX / 8>{});
+      return true;
+    }
   }
   return false;
 }

@@ -70,7 +70,10 @@ def test_column_variant_table_on_host(lib):
                                                          (8, 32, 1, 16), (4, 16, 1, 16)]
     assert b.column_variants(b.PST_FP32, 8192, True) == [(2, 16, 0, 16), (2, 32, 1, 16), (2, 16, 1, 16),
                                                          (4, 32, 1, 16), (2, 16, 1, 16)]
-    assert b.column_variants(b.PST_FP32, 4096, False) == [(4, 16, 0, 16), (2, 16, 0, 16)]
+    assert b.column_variants(b.PST_FP32, 4096, False) == [(4, 16, 0, 16), (2, 16, 0, 16), (1, 16, 0, 16)]
+    assert b.column_variants(b.PST_FP32, 1024, False) == [(16, 16, 0, 16), (8, 16, 0, 16), (4, 16, 0, 16),
+                                                          (2, 16, 0, 16)]
+    assert b.column_variants(b.PST_FP32, 256, False) == [(16, 16, 0, 16), (8, 16, 0, 16)]
     assert b.column_variants(b.PST_FP64, 4096, True) == [(2, 16, 0, 16), (1, 16, 0, 16), (2, 32, 1, 16),
                                                          (2, 16, 1, 16), (4, 16, 1, 16), (2, 8, 1, 8)]
     assert b.column_variants(b.PST_FP64, 8192, True) == [(1, 16, 0, 16), (1, 16, 0, 16), (1, 32, 1, 16),

@@ -125,7 +125,7 @@ def test_energy_enstrophy(prec):
     assert abs(q[1, 1] / ons.enstrophy(w0[1], 1, 1) - 1) < tq
 
 
-@pytest.mark.parametrize("n,variant", [(1024, 0), (1024, 1), (2048, 0), (2048, 1)])
+@pytest.mark.parametrize("n,variant", [(1024, v) for v in range(4)] + [(2048, v) for v in range(4)])
 def test_full_size_random_phase_short(n, variant):
     # benchmark grids (uneven batch members) in both column variants, FP32,
     # fixed 2 iterations, 4 steps

@@ -98,7 +98,7 @@ def test_initial_hamiltonian_closed_form():
     assert abs(h[0] - (A * A * math.pi / 2 + series)) < 1e-12 and h[1] == 0.0
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_batch_of_16_at_2048_alone_vs_batch_bitwise(variant):
     # Benchmark configuration: 16 seeds of 2048^2 FP32 in one launch, in both
     # column variants (the benchmark runs the autotuner's pick).  Sampled
