@@ -49,8 +49,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 # algorithmic bytes per grid point (FP32; FP64 doubles them)
 NLS_PASS_BYTES = 16            # read + write of one complex value
-SG_ROW_BYTES, SG_COL_BYTES = 20, 12
-NS_COL_BYTES, NS_ROW_BYTES = 32, 20
+SG_ROW_BYTES, SG_COL_BYTES = 28, 12   # increment form: W, u, d in; u, d, U, S out
+NS_COL_BYTES, NS_ROW_BYTES = 36, 20   # per fixed-point iteration
 SECTIONS = ("fp32", "sg", "ns", "sweep", "ablation")
 
 
@@ -66,21 +66,18 @@ SG_SOURCES = ("fft_line.hpp", "kernels.hpp", "k_sg.hip", "pst_common.hpp")
 NS_SOURCES = ("fft_line.hpp", "kernels.hpp", "k_ns.hip", "pst_common.hpp")
 
 
-def traffic_from_profile(kernel: str, column_variant: int, name: str = "nls_4096_fp32_traffic.json",
-                         sources=None):
-    """HBM bytes per launch from a committed counter summary, if it was taken
-    on the current kernel sources and (for a column pass) the same column
-    variant; None otherwise."""
+def traffic_from_profile(kernel: str, variant: int, name: str, sources=None):
+    """HBM bytes per launch of one tile variant of a kernel, from a committed
+    counter summary, if it was taken on the current kernel sources; None
+    otherwise (or when that variant was not counted)."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("source_hash") != (kernel_source_hash(sources) if sources else kernel_source_hash()):
         return None
-    k = rec.get("kernels", {}).get(kernel)
-    if k is None or k.get("column_variant", column_variant) != column_variant:
-        return None
-    return k.get("bytes_per_launch")
+    k = rec.get("kernels", {}).get(kernel, {}).get("variants", {}).get(str(variant))
+    return None if k is None else k.get("bytes_per_launch")
 
 
 def progress(msg: str) -> None:
@@ -117,7 +114,8 @@ def measure_nls(b, inputs, n, prec, K, W, traffic_file=None):
     d = inputs.PAPER_DOMAIN
     dt, g = 1e-3, 1.0
     plan = b.Plan(n, n, b.PST_C2C, prec, 1)
-    col_variant = plan.autotune("nls")
+    plan.autotune("nls")
+    row_variant, col_variant = plan.variants()
     psi = torch.from_numpy(inputs.nls_gaussian(n, n, d, seed=0)).to("cuda", plan.complex_dtype)
     psi = psi.reshape(1, n, n).contiguous()
     q0 = plan.conserved_quantities("nls", psi, d=d, dt=dt, g=g)
@@ -142,7 +140,8 @@ def measure_nls(b, inputs, n, prec, K, W, traffic_file=None):
     alg_bytes = NLS_PASS_BYTES * esz * n * n
     achieved = alg_bytes / avg_s / 1e9
     kname = {"nls_row": "k_nls_row", "nls_col": "k_nls_col"}[dom]
-    traffic = traffic_from_profile(kname, col_variant, traffic_file) if traffic_file else None
+    traffic = traffic_from_profile(kname, {"nls_row": row_variant, "nls_col": col_variant}[dom],
+                                   traffic_file) if traffic_file else None
     out = {
         "value": value, "ms_per_step": el / K * 1e3,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -150,7 +149,7 @@ def measure_nls(b, inputs, n, prec, K, W, traffic_file=None):
                      "avg_launch_us": avg_s * 1e6, "bytes_per_launch_alg": alg_bytes},
         "pct_hbm_roofline_step": value * 2 * NLS_PASS_BYTES * esz / (HBM_PEAK_GBS * 1e9),
         "passes_avg_us": {k: (v[0] / max(v[1], 1)) * 1e3 for k, v in passes.items()},
-        "column_variant": col_variant,
+        "column_variant": col_variant, "row_variant": row_variant,
         "mass_rel_drift": float(q1[0, 0] / q0[0, 0] - 1),
         "energy_rel_drift": float(q1[0, 1] / q0[0, 1] - 1),
     }
@@ -191,7 +190,7 @@ def bench_sg(b, inputs):
     rate = pts * timed / el
     row_s, col_s = r[0] / r[1] / 1e3, c[0] / c[1] / 1e3
     row_alg, col_alg = SG_ROW_BYTES * pts, SG_COL_BYTES * pts
-    rt = traffic_from_profile("k_sg_row", variant, "sg_2048x16_fp32_traffic.json", SG_SOURCES)
+    rt = traffic_from_profile("k_sg_row", 0, "sg_2048x16_fp32_traffic.json", SG_SOURCES)
     ct = traffic_from_profile("k_sg_col", variant, "sg_2048x16_fp32_traffic.json", SG_SOURCES)
     return {"pt_steps_per_s": rate, "ms_per_step": el / timed * 1e3, "steps_timed": timed,
             "alg_bytes_per_pt_step": SG_ROW_BYTES + SG_COL_BYTES,

@@ -1,4 +1,5 @@
 """bench.py's command line and host-side helpers (no GPU needed)."""
+import json
 import os
 import subprocess
 import sys
@@ -40,4 +41,13 @@ def test_kernel_source_hash_covers_the_nls_sources():
     import bench
     h = bench.kernel_source_hash()
     assert len(h) == 16 and int(h, 16) >= 0
-    assert bench.traffic_from_profile("k_nls_col", 99) is None  # another column variant
+    # a variant that was not counted has no record; the counted ones carry bytes only while the
+    # kernel sources hash matches the one recorded with them
+    assert bench.traffic_from_profile("k_nls_col", 99, "nls_4096_fp64_traffic.json") is None
+    assert bench.traffic_from_profile("k_nls_col", 0, "no_such_profile.json") is None
+    rec = json.load(open(os.path.join(bench.ROOT, "profiles", "nls_4096_fp64_traffic.json")))
+    got = bench.traffic_from_profile("k_nls_col", 4, "nls_4096_fp64_traffic.json")
+    if rec["source_hash"] == h:
+        assert got == rec["kernels"]["k_nls_col"]["variants"]["4"]["bytes_per_launch"]
+    else:
+        assert got is None
