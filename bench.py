@@ -49,8 +49,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 # algorithmic bytes per grid point (FP32; FP64 doubles them)
 NLS_PASS_BYTES = 16            # read + write of one complex value
-SG_ROW_BYTES, SG_COL_BYTES = 28, 12   # increment form: W, u, d in; u, d, U, S out
-NS_COL_BYTES, NS_ROW_BYTES = 36, 20   # per fixed-point iteration
+SG_ROW_BYTES, SG_COL_BYTES = 20, 12   # the method's bytes (level form); the increment form moves 28 in the row pass
+NS_COL_BYTES, NS_ROW_BYTES = 32, 20   # per fixed-point iteration; the increment form reads 4 more
 SECTIONS = ("fp32", "sg", "ns", "sweep", "ablation")
 
 
