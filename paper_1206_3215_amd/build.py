@@ -4,7 +4,8 @@
 
 Every csrc/*.hip and csrc/*.cpp is compiled by hipcc to _build/*.o (in
 parallel) and linked into paper_1206_3215_amd/libpst.so.  Without --force,
-objects newer than their source and every header are reused.
+objects newer than their source and every header are reused.  Rebuilt
+device code is then checked by store_audit (a gfx950 store hazard).
 """
 from __future__ import annotations
 
@@ -81,6 +82,18 @@ def build(force: bool = False, jobs: int | None = None, verbose: bool = True) ->
         os.replace(tmp, LIB)
         if verbose:
             print(f"[build] linked {os.path.relpath(LIB, ROOT)}", flush=True)
+    if todo:
+        # every rebuilt device object must be free of the wide-store hazard
+        from paper_1206_3215_amd import store_audit
+        bad = store_audit.audit([o for s, o in todo if s.endswith(".hip")])
+        if bad:
+            for b in bad[:20]:
+                print(" | ".join(str(x) for x in b), file=sys.stderr)
+            os.remove(LIB)
+            raise RuntimeError(f"{len(bad)} wide store(s) whose data registers are overwritten too early "
+                               "(see paper_1206_3215_amd/store_audit.py)")
+        if verbose:
+            print("[build] store audit clean", flush=True)
     return LIB
 
 

@@ -31,13 +31,13 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_nls_cq_row(
   m2 = line_sum(red, lid, t, G::TL, m2);
   m4 = line_sum(red, lid, t, G::TL, m4);
   if (valid && t == 0) {
-    part[2 * (size_t)line] = m2;
-    part[2 * (size_t)line + 1] = m4;
+    store1(part + 2 * (size_t)line, m2);
+    store1(part + 2 * (size_t)line + 1, m4);
   }
   line_fft<N, false>(v, L, t, tw);
   if (valid) {
 #pragma unroll
-    for (int s = 0; s < G::R; ++s) spec[(size_t)line * N + t + s * G::TL] = v[s];
+    for (int s = 0; s < G::R; ++s) gstore(spec + ((size_t)line * N + t + s * G::TL), v[s]);
   }
 }
 
@@ -95,10 +95,10 @@ __global__ __launch_bounds__(256) void k_nls_cq_finish(int ny, int nx, const dou
     const double mass = dxdy * a;
     const double kin = kin_coef * c;
     const double pot = 0.25 * g * dxdy * b;
-    out[4 * f + 0] = mass;
-    out[4 * f + 1] = kin + pot;
-    out[4 * f + 2] = kin;
-    out[4 * f + 3] = pot;
+    store1(out + 4 * f + 0, mass);
+    store1(out + 4 * f + 1, kin + pot);
+    store1(out + 4 * f + 2, kin);
+    store1(out + 4 * f + 3, pot);
     if (!isfinite(mass) || !isfinite(kin + pot)) atomicOr(status, (int)ST_NONFINITE);
   }
 }

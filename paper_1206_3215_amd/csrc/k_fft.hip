@@ -24,7 +24,7 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_row_c2c(
   if (valid) {
     cpx<T>* dst = out + (size_t)line * N;
 #pragma unroll
-    for (int s = 0; s < G::R; ++s) dst[t + s * G::TL] = v[s] * scale;
+    for (int s = 0; s < G::R; ++s) gstore(dst + (t + s * G::TL), v[s] * scale);
   }
 }
 
@@ -92,8 +92,8 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_row_r2c(
     const cpx<T> zk = L[lds_idx(k)];
     const cpx<T> zm = conj(L[lds_idx((N - k) & (N - 1))]);
     const cpx<T> sum = zk + zm, dif = zk - zm;
-    if (va) oa[k] = sum * T(0.5);
-    if (vb) ob[k] = cpx<T>{dif.im, -dif.re} * T(0.5);
+    if (va) gstore(oa + k, sum * T(0.5));
+    if (vb) gstore(ob + k, cpx<T>{dif.im, -dif.re} * T(0.5));
   }
 }
 

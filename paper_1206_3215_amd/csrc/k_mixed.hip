@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kMxThreads) void k_mx_row_c2c(const cpx<T>* in, cpx
   const cpx<T>* res = mx_fft<INV>(A, B, W, ml, tw);
   for (int i = threadIdx.x; i < W * n; i += blockDim.x) {
     const int c = i / n, e = i % n;
-    if (l0 + c < nlines) out[(size_t)(l0 + c) * n + e] = res[e * W + c] * scale;
+    if (l0 + c < nlines) gstore(out + ((size_t)(l0 + c) * n + e), res[e * W + c] * scale);
   }
 }
 
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(kMxThreads) void k_mx_col_c2c(const cpx<T>* src, cp
   const cpx<T>* res = mx_fft<INV>(A, B, W, ml, tw);
   for (int i = threadIdx.x; i < W * n; i += blockDim.x) {
     const int e = i / W, c = i % W;
-    if (col0 + c < ncols) dst[fo + (size_t)e * ld + col0 + c] = res[e * W + c] * scale;
+    if (col0 + c < ncols) gstore(dst + (fo + (size_t)e * ld + col0 + c), res[e * W + c] * scale);
   }
 }
 
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kMxThreads) void k_mx_row_r2c(const T* in, cpx<T>* 
   const cpx<T>* res = mx_fft<false>(A, B, W, ml, tw);
   for (int i = threadIdx.x; i < W * h; i += blockDim.x) {
     const int c = i / h, e = i % h;
-    if (l0 + c < nlines) out[(size_t)(l0 + c) * h + e] = res[e * W + c];
+    if (l0 + c < nlines) gstore(out + ((size_t)(l0 + c) * h + e), res[e * W + c]);
   }
 }
 
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(kMxThreads) void k_mx_row_c2r(const cpx<T>* in, T* 
   const cpx<T>* res = mx_fft<true>(A, B, W, ml, tw);
   for (int i = threadIdx.x; i < W * n; i += blockDim.x) {
     const int c = i / n, e = i % n;
-    if (l0 + c < nlines) out[(size_t)(l0 + c) * n + e] = res[e * W + c].re * scale;
+    if (l0 + c < nlines) store1(out + ((size_t)(l0 + c) * n + e), res[e * W + c].re * scale);
   }
 }
 
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(kMxThreads) void k_mx_nls_row(FieldRef psi, int nli
     const int c = i / n, e = i % n;
     if (l0 + c < nlines) {
       const cpx<T> v = MODE == 1 ? res[e * W + c] : res[e * W + c] * scale;
-      row(l0 + c)[e] = v;
+      gstore(row(l0 + c) + e, v);
       if constexpr (MODE == 2) bad = bad || !finite_c(v);
     }
   }
@@ -292,7 +292,7 @@ __global__ __launch_bounds__(kMxThreads) void k_mx_nls_col(FieldRef psi, int nx,
   const cpx<T>* out = mx_fft<true>(res, res == A ? B : A, W, ml, tw);
   for (int i = threadIdx.x; i < W * n; i += blockDim.x) {
     const int e = i / W, c = i % W;
-    if (col0 + c < nx) f[(size_t)e * nx + col0 + c] = out[i];
+    if (col0 + c < nx) gstore(f + ((size_t)e * nx + col0 + c), out[i]);
   }
 }
 
@@ -319,11 +319,11 @@ __global__ __launch_bounds__(kMxThreads) void k_mx_cq_row(const cpx<T>* psi, cpx
   m2 = line_sum(red, 0, threadIdx.x, kMxThreads, m2);
   m4 = line_sum(red, 0, threadIdx.x, kMxThreads, m4);
   if (threadIdx.x == 0) {
-    part[2 * (size_t)line] = m2;
-    part[2 * (size_t)line + 1] = m4;
+    store1(part + 2 * (size_t)line, m2);
+    store1(part + 2 * (size_t)line + 1, m4);
   }
   const cpx<T>* res = mx_fft<false>(A, B, 1, ml, tw);
-  for (int e = threadIdx.x; e < n; e += blockDim.x) spec[(size_t)line * n + e] = res[e];
+  for (int e = threadIdx.x; e < n; e += blockDim.x) gstore(spec + ((size_t)line * n + e), res[e]);
 }
 
 template <typename T>

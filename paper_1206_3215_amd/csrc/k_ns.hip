@@ -215,8 +215,8 @@ __global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_ns_col(const cpx
       res = line_sum(red, c, t, G::TL, res * wt);
       ens = line_sum(red, c, t, G::TL, ens * wt);
       if (valid && t == 0) {
-        part[2 * ((size_t)field * ncols + col)] = res;
-        part[2 * ((size_t)field * ncols + col) + 1] = ens;
+        store1(part + 2 * ((size_t)field * ncols + col), res);
+        store1(part + 2 * ((size_t)field * ncols + col) + 1, ens);
       }
     }
     // derivative hybrids of w: psi_y, omega_x, psi_x, omega_y
@@ -285,8 +285,8 @@ __global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_ns_col(const cpx
         resn = line_sum(red, c, t, G::TL, resn);
         ensn = line_sum(red, c, t, G::TL, ensn);
         if (pk && t == 0) {
-          part[2 * ((size_t)field * ncols + nh)] = resn;
-          part[2 * ((size_t)field * ncols + nh) + 1] = ensn;
+          store1(part + 2 * ((size_t)field * ncols + nh), resn);
+          store1(part + 2 * ((size_t)field * ncols + nh) + 1, ensn);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -418,8 +418,8 @@ __global__ __launch_bounds__((WT * (N / line_radix(N)))) void k_ns_cq_col(const 
   en = line_sum(red, c, t, G::TL, en * wt);
   zz = line_sum(red, c, t, G::TL, zz * wt);
   if (valid && t == 0) {
-    part[2 * ((size_t)field * ncols + col)] = en;
-    part[2 * ((size_t)field * ncols + col) + 1] = zz;
+    store1(part + 2 * ((size_t)field * ncols + col), en);
+    store1(part + 2 * ((size_t)field * ncols + col) + 1, zz);
   }
 }
 
@@ -435,10 +435,10 @@ __global__ __launch_bounds__(256) void k_ns_cq_finish(int ncols, const double* p
   a = line_sum(red, 0, t, 256, a);
   b = line_sum(red, 0, t, 256, b);
   if (t == 0) {
-    out[4 * f + 0] = en_coef * a;
-    out[4 * f + 1] = zz_coef * b;
-    out[4 * f + 2] = 0.0;
-    out[4 * f + 3] = 0.0;
+    store1(out + 4 * f + 0, en_coef * a);
+    store1(out + 4 * f + 1, zz_coef * b);
+    store1(out + 4 * f + 2, 0.0);
+    store1(out + 4 * f + 3, 0.0);
     if (!isfinite(a) || !isfinite(b)) atomicOr(status, (int)ST_NONFINITE);
   }
 }

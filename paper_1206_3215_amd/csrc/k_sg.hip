@@ -224,8 +224,8 @@ __global__ __launch_bounds__((RowGeom<T, N>::THREADS)) void k_sg_h_row(
   kin = line_sum(red, lid, t, G::TL, kin);
   pot = line_sum(red, lid, t, G::TL, pot);
   if (t == 0 && va) {
-    part[4 * (size_t)pair] = kin;
-    part[4 * (size_t)pair + 1] = pot;
+    store1(part + 4 * (size_t)pair, kin);
+    store1(part + 4 * (size_t)pair + 1, pot);
   }
   line_fft<N, false>(ub, L, t, tw);
   store_pair_halves<T, N>(ub, L, t, UB + (size_t)la * H, UB + (size_t)lb * H, va, vb);
@@ -281,10 +281,10 @@ __global__ __launch_bounds__(256) void k_sg_h_finish(int npairs, int ncols, cons
   c = line_sum(red, 0, t, 256, c);
   if (t == 0) {
     const double kin = 0.5 * dxdy * a, pot = dxdy * b, grad = grad_coef * c;
-    out[4 * f + 0] = kin + grad + pot;
-    out[4 * f + 1] = kin;
-    out[4 * f + 2] = grad;
-    out[4 * f + 3] = pot;
+    store1(out + 4 * f + 0, kin + grad + pot);
+    store1(out + 4 * f + 1, kin);
+    store1(out + 4 * f + 2, grad);
+    store1(out + 4 * f + 3, pot);
     if (!isfinite(kin + grad + pot)) atomicOr(status, (int)ST_NONFINITE);
   }
 }

@@ -244,8 +244,30 @@ template <typename P>
 __device__ __forceinline__ gptr<P> field(const FieldRef& f, int i) {
   return (gptr<P>)f.at(i);
 }
+// Stores write at most 8 bytes per lane.  On gfx950 a vector memory store
+// of 16 bytes whose data registers the next VALU instruction overwrites can
+// write the new values (observed as run-to-run differences in FP64 results:
+// the compiler put no wait state between the two), so 16-byte values go out
+// as two 8-byte halves, and every store made through these helpers uses an
+// address the compiler cannot relate to its neighbours', so that it does not
+// merge adjacent stores back into one wide access.
+template <typename P>
+__device__ __forceinline__ gptr<P> unmerged(gptr<P> p) {
+  asm volatile("" : "+v"(p));
+  return p;
+}
+template <typename T>
+__device__ __forceinline__ void store1(gptr<T> p, T v) {
+  static_assert(sizeof(T) <= 8, "stores write at most 8 bytes");
+  *unmerged(p) = v;
+}
+template <typename T>
+__device__ __forceinline__ void store1(T* p, T v) {
+  store1((gptr<T>)p, v);
+}
+
 // Load and store of a complex value through a global pointer (one 8- or
-// 16-byte access each).
+// 16-byte load; one or two 8-byte stores).
 template <typename T>
 __device__ __forceinline__ cpx<T> gload(gptr<const cpx<T>> p) {
   using V = T __attribute__((ext_vector_type(2)));
@@ -258,14 +280,27 @@ __device__ __forceinline__ cpx<T> gload(gptr<cpx<T>> p) {
 }
 template <typename T>
 __device__ __forceinline__ void gstore(gptr<cpx<T>> p, cpx<T> v) {
-  using V = T __attribute__((ext_vector_type(2)));
-  *(gptr<V>)p = V{v.re, v.im};
+  if constexpr (sizeof(T) == 4) {
+    using V = T __attribute__((ext_vector_type(2)));
+    store1((gptr<V>)p, V{v.re, v.im});
+  } else {
+    store1((gptr<T>)p, v.re);
+    store1((gptr<T>)p + 1, v.im);
+  }
+}
+template <typename T>
+__device__ __forceinline__ void gstore(cpx<T>* p, cpx<T> v) {
+  gstore((gptr<cpx<T>>)p, v);
 }
 
 // Buffer-resource access to one field (at most 2 GiB): 32-bit byte offsets,
 // a per-lane part (voff) and a wave-uniform part (soff, kept in a scalar
 // register), so a thread's many strided accesses cost no 64-bit address
 // registers.  Word 3 of the descriptor is the gfx9 raw-buffer format.
+// 16-byte stores (an FP64 complex value, or two FP32 ones) are issued from
+// an asm statement that ends with two wait states, so that no instruction
+// can overwrite the data registers right behind the store (the hazard
+// described above); the compiler sees the statement as a store to memory.
 struct FieldBuf {
   __amdgpu_buffer_rsrc_t r;
   __device__ FieldBuf(const void* base, unsigned bytes)
@@ -286,11 +321,17 @@ struct FieldBuf {
     const V a = {v.re, v.im};
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, a), r, voff, soff, 0);
   }
+  __device__ __forceinline__ void st16(unsigned voff, unsigned soff,
+                                       unsigned __attribute__((ext_vector_type(4))) data) const {
+    asm volatile("buffer_store_dwordx4 %0, %1, %2, %3 offen\n\ts_nop 1"
+                 :
+                 : "v"(data), "v"(voff), "s"(r), "s"(soff)
+                 : "memory");
+  }
   __device__ __forceinline__ void st(unsigned voff, unsigned soff, cpx<double> v) const {
     using V = double __attribute__((ext_vector_type(2)));
     using U = unsigned __attribute__((ext_vector_type(4)));
-    const V a = {v.re, v.im};
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, a), r, voff, soff, 0);
+    st16(voff, soff, __builtin_bit_cast(U, V{v.re, v.im}));
   }
   template <typename T>
   __device__ __forceinline__ cpx<T> ldc(unsigned voff, unsigned soff) const {
@@ -310,8 +351,7 @@ struct FieldBuf {
   __device__ __forceinline__ void st2(unsigned voff, cpx<float> a, cpx<float> b) const {
     using V = float __attribute__((ext_vector_type(4)));
     using U = unsigned __attribute__((ext_vector_type(4)));
-    const V x = {a.re, a.im, b.re, b.im};
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, x), r, voff, 0, 0);
+    st16(voff, 0, __builtin_bit_cast(U, V{a.re, a.im, b.re, b.im}));
   }
   __device__ __forceinline__ void st2(unsigned voff, cpx<double> a, cpx<double> b) const {
     st(voff, 0, a);
@@ -504,8 +544,8 @@ __device__ __forceinline__ void store_pair_halves(const cpx<T> (&v)[line_radix(N
     const cpx<T> zk = L[lds_idx(k)];
     const cpx<T> zm = conj(L[lds_idx((N - k) & (N - 1))]);
     const cpx<T> sum = zk + zm, dif = zk - zm;
-    if (va) A[k] = sum;
-    if (vb) B[k] = cpx<T>{dif.im, -dif.re};
+    if (va) gstore(A + k, sum);
+    if (vb) gstore(B + k, cpx<T>{dif.im, -dif.re});
   }
   __syncthreads();
 }
