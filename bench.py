@@ -512,6 +512,7 @@ def main():
         "pct_hbm_roofline_step": head["pct_hbm_roofline_step"],
         "passes_avg_us": head["passes_avg_us"],
         "column_variant": head["column_variant"],
+        "row_variant": head["row_variant"],
         "copy_GBps": copy_gbs,
         "mass_rel_drift": head["mass_rel_drift"],
         "energy_rel_drift": head["energy_rel_drift"],
