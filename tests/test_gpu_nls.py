@@ -50,13 +50,17 @@ def test_small_workload_matches_oracle(prec):
     ge = np.array([x[0, 1] for x in gdiag])
     rm = np.array([x[1] for x in rdiag])
     re_ = np.array([x[2] for x in rdiag])
-    # FP32: a single-precision run drifts ~4e-8 per step in mass (documented);
-    # the bar is the FP32 tolerance class.
-    tol_q = 1e-12 if prec == 1 else 1e-4
-    assert np.max(np.abs(gm / rm - 1)) < tol_q
-    assert np.max(np.abs(ge / re_ - 1)) < tol_q
     if prec == 1:
+        assert np.max(np.abs(gm / rm - 1)) < 1e-12
+        assert np.max(np.abs(ge / re_ - 1)) < 1e-12
         assert np.max(np.abs(gm / gm[0] - 1)) < 1e-12   # mass to rounding (paper's Results)
+    else:
+        # FP32 reading: each step applies unit-modulus factors rounded once,
+        # so the mass drifts by at most one single-precision rounding unit per
+        # step; the energy follows the field (FP32 tolerance class)
+        steps = 20 * np.arange(len(gm))
+        assert np.all(np.abs(gm / gm[0] - 1) <= 2.0 ** -23 * np.maximum(steps, 1))
+        assert np.max(np.abs(ge / re_ - 1)) < TOL[0]
 
 
 @pytest.mark.parametrize("prec", [1, 0])
