@@ -247,14 +247,17 @@ void prof_begin(Plan* pl, int pass) {
   if (!pl->prof) return;
   g_prof_start = take_event(pl);
   g_prof_pass = pass;
-  if (g_prof_start) hipEventRecord(g_prof_start, pl->stream);
+  // Profiling is best effort: a pass whose start cannot be recorded is not timed.
+  if (g_prof_start && hipEventRecord(g_prof_start, pl->stream) != hipSuccess) g_prof_start = nullptr;
 }
 
 void prof_end(Plan* pl) {
   if (!pl->prof || g_prof_start == nullptr) return;
   hipEvent_t e = take_event(pl);
-  if (e == nullptr) return;
-  hipEventRecord(e, pl->stream);
+  if (e == nullptr || hipEventRecord(e, pl->stream) != hipSuccess) {
+    g_prof_start = nullptr;
+    return;
+  }
   pl->ev_rec.push_back({g_prof_pass, {g_prof_start, e}});
   g_prof_start = nullptr;
 }
@@ -335,8 +338,9 @@ pst_status pst_set_workspace(pst_plan plan, void* dev_ptr, size_t bytes) {
     return fail(PST_ERR_INVALID, "workspace of %zu bytes is smaller than the %zu needed", bytes, plan->ws_need);
   if (reinterpret_cast<uintptr_t>(dev_ptr) % 256 != 0) return fail(PST_ERR_INVALID, "workspace not 256-byte aligned");
   if (plan->ws_owned) {
-    hipStreamSynchronize(plan->stream);
-    hipFree(plan->ws);
+    pst_status st = hip_check(hipStreamSynchronize(plan->stream), "hipStreamSynchronize");
+    if (st != PST_OK) return st;  // the old workspace may still be in use: keep it
+    (void)hipFree(plan->ws);
   }
   plan->ws = dev_ptr;
   plan->ws_owned = false;
@@ -345,14 +349,15 @@ pst_status pst_set_workspace(pst_plan plan, void* dev_ptr, size_t bytes) {
 
 pst_status fft2d_destroy(pst_plan plan) {
   if (plan == nullptr) return fail(PST_ERR_INVALID, "plan is NULL");
-  hipStreamSynchronize(plan->stream);
-  for (void* p : plan->owned) hipFree(p);
-  for (hipEvent_t e : plan->ev_pool) hipEventDestroy(e);
-  if (plan->ws_owned) hipFree(plan->ws);
-  if (plan->ns_host) hipHostFree(plan->ns_host);
-  if (plan->ns_ev) hipEventDestroy(plan->ns_ev);
+  // The plan is released whatever happens; the first failure is reported.
+  pst_status st = hip_check(hipStreamSynchronize(plan->stream), "hipStreamSynchronize");
+  for (void* p : plan->owned) (void)hipFree(p);
+  for (hipEvent_t e : plan->ev_pool) (void)hipEventDestroy(e);
+  if (plan->ws_owned) (void)hipFree(plan->ws);
+  if (plan->ns_host) (void)hipHostFree(plan->ns_host);
+  if (plan->ns_ev) (void)hipEventDestroy(plan->ns_ev);
   delete plan;
-  return PST_OK;
+  return st;
 }
 
 pst_status fft2d_exec(pst_plan pl, const void* in, void* out, int sign) {

@@ -615,16 +615,16 @@ static pst_status time_launch(Plan* pl, L&& launch, float* ms) {
   pst_status st = PST_OK;
   *ms = 1e30f;
   for (int w = 0; w < 3 && st == PST_OK; ++w) {
-    hipEventRecord(a, s);
+    st = hip_check(hipEventRecord(a, s), "hipEventRecord");
     for (int i = 0; i < 5 && st == PST_OK; ++i) st = hip_check(launch(), "autotune launch");
-    hipEventRecord(b, s);
+    if (st == PST_OK) st = hip_check(hipEventRecord(b, s), "hipEventRecord");
     float t = 0.f;
     if (st == PST_OK) st = hip_check(hipEventSynchronize(b), "hipEventSynchronize");
     if (st == PST_OK) st = hip_check(hipEventElapsedTime(&t, a, b), "hipEventElapsedTime");
     if (st == PST_OK && t < *ms) *ms = t;
   }
-  hipEventDestroy(a);
-  hipEventDestroy(b);
+  (void)hipEventDestroy(a);  // teardown: the timing result is already known
+  (void)hipEventDestroy(b);
   return st;
 }
 
@@ -778,10 +778,11 @@ size_t params_size(int eq) {
 }
 
 void destroy_batch_plan(BatchPlan& bp) {
-  for (auto& g : bp.graphs) hipGraphExecDestroy(g.second);
+  // Teardown of a cache entry: nothing is left to report a failure to.
+  for (auto& g : bp.graphs) (void)hipGraphExecDestroy(g.second);
   bp.graphs.clear();
-  if (bp.pl != nullptr) fft2d_destroy(bp.pl);  // synchronises the stream it last ran on
-  if (bp.last != nullptr) hipEventDestroy(bp.last);
+  if (bp.pl != nullptr) (void)fft2d_destroy(bp.pl);  // synchronises the stream it last ran on
+  if (bp.last != nullptr) (void)hipEventDestroy(bp.last);
   bp.pl = nullptr;
   bp.last = nullptr;
 }
@@ -874,7 +875,7 @@ static pst_status launch_or_replay(BatchPlan& bp, bool capture, const std::vecto
     }
   }
   if (capture && g == bp.graphs.end() && bp.graphs.size() >= kMaxGraphs) {
-    for (auto& e : bp.graphs) hipGraphExecDestroy(e.second);
+    for (auto& e : bp.graphs) (void)hipGraphExecDestroy(e.second);
     bp.graphs.clear();
   }
   if (!capture) {
@@ -890,7 +891,7 @@ static pst_status launch_or_replay(BatchPlan& bp, bool capture, const std::vecto
         if (st == PST_OK) {
           hipGraphExec_t ex;
           st = hip_check(hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0), "graph instantiate");
-          hipGraphDestroy(graph);
+          (void)hipGraphDestroy(graph);  // the instantiated graph does not need it
           if (st == PST_OK) g = bp.graphs.emplace(key, ex).first;
         }
       }
@@ -1140,9 +1141,12 @@ extern "C" pst_status solve_batch(const pst_request* reqs, int n, void* hip_stre
     }
   }
   for (NsGroup& q : ns) jobs[q.ji].bp->pl->batch = q.cap;  // also after an error
-  for (const Job& j : jobs)
-    if (j.bp->used) hipStreamWaitEvent(caller, j.bp->last, 0);
-  hipEventDestroy(fork);
+  for (const Job& j : jobs) {
+    if (!j.bp->used) continue;
+    pst_status w = hip_check(hipStreamWaitEvent(caller, j.bp->last, 0), "join wait");
+    if (result == PST_OK) result = w;
+  }
+  (void)hipEventDestroy(fork);
   return result;
 }
 
