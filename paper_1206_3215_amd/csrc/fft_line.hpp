@@ -11,11 +11,13 @@
 // (j/Ns)*Ns*r + k + q*Ns).  N = f * R^m with the odd-sized radix f (if any)
 // first; a stage of radix r < R runs R/r butterflies per thread.
 //
-// Twiddles of stage s (radix r, Ns = product of earlier radices) are read
-// from a table of (r-1)*Ns entries, entry (q-1)*Ns + k = exp(-2 pi i q k /
-// (Ns r)), computed in double precision on the host and rounded once.  The
-// inverse transform multiplies by their conjugates.  Transforms are
-// unnormalised: forward kernel exp(-i...), inverse exp(+i...).
+// Twiddles of stage s (radix r, Ns = product of earlier radices) come from
+// a table of (r-1)*Ns entries, entry (q-1)*Ns + k = exp(-2 pi i q k /
+// (Ns r)), computed in double precision on the host and rounded once.
+// Single precision reads every entry it uses; double-precision radix-16
+// stages read three entries per butterfly and form the other powers (see
+// derived_twiddles).  The inverse transform multiplies by their conjugates.
+// Transforms are unnormalised: forward kernel exp(-i...), inverse exp(+i...).
 //
 // The radix R of the full stages is a template parameter: 16 by default,
 // or 8 (lines of 64 and more), which halves the values a thread must hold
@@ -248,6 +250,55 @@ __host__ __device__ __forceinline__ cpx<T> tw_load(const cpx<T>* tw, int len, un
 #endif
 }
 
+// Double-precision radix-16 stages after the first read three table
+// entries per butterfly, the powers 1, 4 and 8 of its base twiddle
+// c = exp(-2 pi i k / (16 Ns)), and form the other twelve powers by complex
+// products (at most three products deep, a few units of 2^-53): fifteen
+// table loads per butterfly cost more time than the products.  These loads
+// are issued before the preceding exchange, so their latency hides behind
+// it.  Single precision reads all fifteen entries, each rounded once, which
+// keeps the magnitude error of every twiddle at one rounding.
+template <typename T>
+__host__ __device__ constexpr bool derived_twiddles(int r) {
+  return r == 16 && std::is_same<T, double>::value;
+}
+
+// c^1, c^4 and c^8 for butterfly j of stage S.
+template <int N, int S, int R, typename T>
+__host__ __device__ __forceinline__ void load_roots(cpx<T> (&c)[3], const cpx<T>* __restrict__ tw, int j) {
+  constexpr int Ns = stage_ns(N, R, S);
+  constexpr int toff = tw_base(N, R) + stage_tw_offset(N, R, S);
+  const unsigned k = (unsigned)j & (Ns - 1);
+  c[0] = tw_load(tw, tw_table_total(N), k, (unsigned)toff);
+  c[1] = tw_load(tw, tw_table_total(N), k, (unsigned)(toff + 3 * Ns));
+  c[2] = tw_load(tw, tw_table_total(N), k, (unsigned)(toff + 7 * Ns));
+}
+
+// w[q] *= c^q (forward) or conj(c)^q (inverse), q = 1..15, from c^1, c^4, c^8.
+template <bool INV, typename T>
+__host__ __device__ __forceinline__ void apply_powers(cpx<T>* w, cpx<T> c1, cpx<T> c4, cpx<T> c8) {
+  cpx<T> c[16];
+  c[1] = c1;
+  c[4] = c4;
+  c[8] = c8;
+  c[2] = cmul(c[1], c[1]);
+  c[3] = cmul(c[2], c[1]);
+  c[5] = cmul(c[4], c[1]);
+  c[6] = cmul(c[4], c[2]);
+  c[7] = cmul(c[4], c[3]);
+#pragma unroll
+  for (int q = 9; q < 16; ++q) c[q] = cmul(c[8], c[q - 8]);
+#pragma unroll
+  for (int q = 1; q < 16; ++q) w[q] = INV ? cmul_conj(w[q], c[q]) : cmul(w[q], c[q]);
+}
+
+// Base twiddles of one derived-twiddle stage for a thread's butterflies,
+// loaded while the previous stage's exchange is in progress.
+template <int VPT, int R, typename T>
+struct NextRoots {
+  cpx<T> c[VPT / R > 0 ? VPT / R : 1][3];
+};
+
 // One Stockham stage for thread t.  A thread owns VPT values (VPT a
 // multiple of every stage radix; TL = N/VPT threads per line) and runs VPT/r
 // butterflies of the stage; outputs either stay in registers (last stage) or
@@ -256,7 +307,8 @@ __host__ __device__ __forceinline__ cpx<T> tw_load(const cpx<T>* tw, int len, un
 // wait in the consumed input registers meanwhile.
 template <int N, int S, bool INV, int WS, int VPT, bool SPLIT, int R, typename T>
 __host__ __device__ __forceinline__ void line_stage(cpx<T> (&v)[VPT], void* ldsv, int t,
-                                                    const cpx<T>* __restrict__ tw) {
+                                                    const cpx<T>* __restrict__ tw,
+                                                    const NextRoots<VPT, R, T>& pre) {
   static_assert(R == line_radix(N) || (R == 8 && has_radix8(N)), "no twiddle layout for this radix");
   constexpr int TL = N / VPT;
   constexpr int r = stage_radix(N, R, S);
@@ -272,12 +324,16 @@ __host__ __device__ __forceinline__ void line_stage(cpx<T> (&v)[VPT], void* ldsv
 #pragma unroll
     for (int q = 0; q < r; ++q) w[q] = v[b + q * B];
     if constexpr (Ns > 1) {
-      const unsigned k = (unsigned)j & (Ns - 1);
+      if constexpr (derived_twiddles<T>(r)) {
+        apply_powers<INV>(w, pre.c[b][0], pre.c[b][1], pre.c[b][2]);
+      } else {
+        const unsigned k = (unsigned)j & (Ns - 1);
 #pragma unroll
-      for (int q = 1; q < r; ++q) {
-        // uniform base toff + (q-1) Ns, per-lane offset k
-        const cpx<T> c = tw_load(tw, tw_table_total(N), k, (unsigned)(toff + (q - 1) * Ns));
-        w[q] = INV ? cmul_conj(w[q], c) : cmul(w[q], c);
+        for (int q = 1; q < r; ++q) {
+          // uniform base toff + (q-1) Ns, per-lane offset k
+          const cpx<T> c = tw_load(tw, tw_table_total(N), k, (unsigned)(toff + (q - 1) * Ns));
+          w[q] = INV ? cmul_conj(w[q], c) : cmul(w[q], c);
+        }
       }
     }
     dft<r, INV>(w);
@@ -340,10 +396,18 @@ __host__ __device__ __forceinline__ void line_read_part(cpx<T> (&v)[VPT], const 
 }
 
 template <int N, int S, bool INV, int WS, int VPT, bool SPLIT, int R, typename T>
-__device__ __forceinline__ void line_stages(cpx<T> (&v)[VPT], void* lds, int t, const cpx<T>* __restrict__ tw) {
+__device__ __forceinline__ void line_stages(cpx<T> (&v)[VPT], void* lds, int t, const cpx<T>* __restrict__ tw,
+                                            const NextRoots<VPT, R, T>& pre) {
   if constexpr (S < num_stages(N, R)) {
-    line_stage<N, S, INV, WS, VPT, SPLIT, R>(v, lds, t, tw);
+    line_stage<N, S, INV, WS, VPT, SPLIT, R>(v, lds, t, tw, pre);
     if constexpr (S < num_stages(N, R) - 1) {
+      // the next stage's base twiddles are in flight during the exchange
+      NextRoots<VPT, R, T> nxt;
+      if constexpr (derived_twiddles<T>(R)) {
+        constexpr int TL = N / VPT;
+#pragma unroll
+        for (int b = 0; b < VPT / R; ++b) load_roots<N, S + 1, R>(nxt.c[b], tw, t + b * TL);
+      }
       __syncthreads();
       if constexpr (SPLIT) {
         line_read_part<N, WS, VPT, false>(v, static_cast<const T*>(lds), t);
@@ -355,7 +419,7 @@ __device__ __forceinline__ void line_stages(cpx<T> (&v)[VPT], void* lds, int t, 
         line_read<N, WS, VPT>(v, static_cast<const cpx<T>*>(lds), t);
       }
       __syncthreads();
-      line_stages<N, S + 1, INV, WS, VPT, SPLIT, R>(v, lds, t, tw);
+      line_stages<N, S + 1, INV, WS, VPT, SPLIT, R>(v, lds, t, tw, nxt);
     }
   }
 }
@@ -367,7 +431,7 @@ __device__ __forceinline__ void line_stages(cpx<T> (&v)[VPT], void* lds, int t, 
 template <int N, bool INV, int WS = 1, int VPT = line_radix(N), bool SPLIT = false, int R = line_radix(N),
           typename T>
 __device__ __forceinline__ void line_fft(cpx<T> (&v)[VPT], void* lds, int t, const cpx<T>* __restrict__ tw) {
-  line_stages<N, 0, INV, WS, VPT, SPLIT, R>(v, lds, t, tw);
+  line_stages<N, 0, INV, WS, VPT, SPLIT, R>(v, lds, t, tw, NextRoots<VPT, R, T>{});
 }
 
 }  // namespace pst

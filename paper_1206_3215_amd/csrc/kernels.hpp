@@ -61,7 +61,8 @@ struct ColGeom {
 // cap.  Otherwise variant 1 is half of variant 0's W, and single-field FP64
 // passes of 4096 and more add 2, variant 0's W with 32 values per thread
 // and the split exchange (registers capped for 2 waves per SIMD); 3, variant
-// 0's W with the split exchange (two blocks per CU); 4, twice that W (full
+// 0's W with the split exchange and registers capped for 4 waves per SIMD
+// (two blocks per CU); 4, twice that W (full
 // 128-byte row segments, one 1024-thread block per CU); 5, variant 0's W at
 // radix 8 (8 values per thread, twice the threads) with the split exchange.
 template <typename T, int N>
@@ -121,7 +122,7 @@ bool dispatch_col1(int var, F&& f) {
       return true;
     }
     if (var == 3) {
-      f(ColCfg<CT::WMAX, 16, true>{});
+      f(ColCfg<CT::WMAX, 16, true, 4>{});
       return true;
     }
     if (var == 4) {
