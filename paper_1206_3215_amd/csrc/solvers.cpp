@@ -602,9 +602,11 @@ std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int>, std::pair<int, int>> g_tuned;
 }  // namespace
 
-// Time of 5 back-to-back launches of `launch` after one warm-up: the best
-// of three such windows (a single window is at the mercy of clock ramps and
-// other work on the device).
+// Time per launch of `launch`: after one warm-up, a first window of 5
+// back-to-back launches sizes the windows to about 1 ms of work (5 to 200
+// launches; short launches are otherwise dominated by launch gaps), then
+// the best of three such windows (a single window is at the mercy of clock
+// ramps and other work on the device).
 template <class L>
 static pst_status time_launch(Plan* pl, L&& launch, float* ms) {
   hipStream_t s = pl->stream;
@@ -613,15 +615,21 @@ static pst_status time_launch(Plan* pl, L&& launch, float* ms) {
   TRY(hip_check(hipEventCreate(&a), "hipEventCreate"));
   TRY(hip_check(hipEventCreate(&b), "hipEventCreate"));
   pst_status st = PST_OK;
+  auto window = [&](int reps, float* t) {
+    st = hip_check(hipEventRecord(a, s), "hipEventRecord");
+    for (int i = 0; i < reps && st == PST_OK; ++i) st = hip_check(launch(), "autotune launch");
+    if (st == PST_OK) st = hip_check(hipEventRecord(b, s), "hipEventRecord");
+    if (st == PST_OK) st = hip_check(hipEventSynchronize(b), "hipEventSynchronize");
+    if (st == PST_OK) st = hip_check(hipEventElapsedTime(t, a, b), "hipEventElapsedTime");
+  };
+  float first = 0.f;
+  window(5, &first);
+  const int reps = first > 0.f ? std::min(200, std::max(5, (int)std::ceil(5.0f / first))) : 5;
   *ms = 1e30f;
   for (int w = 0; w < 3 && st == PST_OK; ++w) {
-    st = hip_check(hipEventRecord(a, s), "hipEventRecord");
-    for (int i = 0; i < 5 && st == PST_OK; ++i) st = hip_check(launch(), "autotune launch");
-    if (st == PST_OK) st = hip_check(hipEventRecord(b, s), "hipEventRecord");
     float t = 0.f;
-    if (st == PST_OK) st = hip_check(hipEventSynchronize(b), "hipEventSynchronize");
-    if (st == PST_OK) st = hip_check(hipEventElapsedTime(&t, a, b), "hipEventElapsedTime");
-    if (st == PST_OK && t < *ms) *ms = t;
+    window(reps, &t);
+    if (st == PST_OK && t / reps < *ms) *ms = t / reps;
   }
   (void)hipEventDestroy(a);  // teardown: the timing result is already known
   (void)hipEventDestroy(b);
