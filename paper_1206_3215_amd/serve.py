@@ -98,10 +98,20 @@ class Report:
 
 
 class Server:
-    def __init__(self, executor, budget_bytes: int, chunk: int = 50):
+    """Continuous batching: every admitted request advances by up to `chunk`
+    steps per round, all of them in one executor call.  With age_s set, a
+    request that has waited a seconds since its arrival advances by
+    chunk * min(max_boost, 1 + a / age_s) steps instead, so the rounds drift
+    from sharing the device equally (which stretches the largest requests)
+    towards serving the oldest first."""
+
+    def __init__(self, executor, budget_bytes: int, chunk: int = 50, age_s: float | None = None,
+                 max_boost: int = 8):
         self.ex = executor
         self.budget = budget_bytes
         self.chunk = chunk
+        self.age_s = age_s
+        self.max_boost = max_boost
 
     def run(self, requests, realtime: bool = True) -> Report:
         """Serve `requests` (arrival_s relative to the start).  With
@@ -170,7 +180,12 @@ class Server:
                 if pending and realtime:
                     time.sleep(max(0.0, min(0.01, pending[0].arrival_s - now())))
                 continue
-            work = [(j.state, min(self.chunk, j.remaining)) for j in batch]
+            if self.age_s:
+                t = time.perf_counter() - t0
+                boost = [min(self.max_boost, 1 + int(max(0.0, t - j.req.arrival_s) / self.age_s)) for j in batch]
+            else:
+                boost = [1] * len(batch)
+            work = [(j.state, min(self.chunk * w, j.remaining)) for j, w in zip(batch, boost)]
             # the device advances this chunk while arrivals are admitted
             errors = []
             statuses = []
@@ -318,11 +333,26 @@ class GpuExecutor:
         st.clear()
 
 
+def fifo_latencies(requests, service_s: dict) -> dict:
+    """Latencies of a single first-in-first-out server that runs each request
+    alone for service_s[rid] seconds, with the requests' arrival times: a
+    request starts when it has arrived and the previous one has finished
+    (the Lindley recursion).  Returns {rid: finish - arrival}."""
+    out = {}
+    free = 0.0
+    for r in sorted(requests, key=lambda r: (r.arrival_s, r.rid)):
+        start = max(r.arrival_s, free)
+        free = start + service_s[r.rid]
+        out[r.rid] = free - r.arrival_s
+    return out
+
+
 def fifo_baseline(requests, params: ServeParams | None = None, fp64: bool = False):
     """The plain path: each request alone, in arrival order, on its own plan
     (the same C-ABI entry points, one simulation per call).  Only the device
     solve of each request is timed (initial conditions and uploads are not).
-    Returns (summed solve seconds, pt-steps/s, results by rid)."""
+    Returns (summed solve seconds, pt-steps/s, results by rid, solve seconds
+    by rid)."""
     import torch
 
     from . import binding as b
@@ -331,6 +361,7 @@ def fifo_baseline(requests, params: ServeParams | None = None, fp64: bool = Fals
     prec = b.PST_FP64 if fp64 else b.PST_FP32
     plans = {}
     results = {}
+    service = {}
     busy = 0.0
     for r in sorted(requests, key=lambda r: r.arrival_s):
         ic = initial_condition(r)
@@ -361,7 +392,8 @@ def fifo_baseline(requests, params: ServeParams | None = None, fp64: bool = Fals
             plan.ns_step(f, inputs.NS_DOMAIN, p.ns_dt, p.ns_nu, r.steps, tol=p.ns_tol, max_iter=p.ns_max_iter)
             out = f
         torch.cuda.synchronize()
-        busy += time.perf_counter() - t0
+        service[r.rid] = time.perf_counter() - t0
+        busy += service[r.rid]
         results[r.rid] = out[0].cpu().numpy()
     pts = float(sum(r.n * r.n * r.steps for r in requests))
-    return busy, pts / busy, results
+    return busy, pts / busy, results, service

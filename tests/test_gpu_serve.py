@@ -33,7 +33,7 @@ def test_served_results_equal_alone_and_oracle(fp64, tol):
     ex = GpuExecutor(fp64=fp64)
     budget = 6 * 40 * 256 * 256 * (2 if fp64 else 1)      # admission binds
     rep = Server(ex, budget_bytes=budget, chunk=16).run(reqs, realtime=True)
-    _, _, alone = fifo_baseline(reqs, fp64=fp64)
+    _, _, alone, _ = fifo_baseline(reqs, fp64=fp64)
     assert len(rep.jobs) == len(reqs)
     worst = {}
     for j in rep.jobs:

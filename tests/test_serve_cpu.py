@@ -7,7 +7,7 @@ import pytest
 
 from oracle import nls as onls, ns as ons, sg as osg
 from paper_1206_3215_amd import inputs
-from paper_1206_3215_amd.serve import BYTES_PER_POINT, Server, ServeParams, initial_condition
+from paper_1206_3215_amd.serve import BYTES_PER_POINT, Server, ServeParams, fifo_latencies, initial_condition
 
 P = ServeParams()
 D = inputs.PAPER_DOMAIN
@@ -174,5 +174,39 @@ def test_executor_overhead_counts_against_budget():
     rep = Server(ex, budget_bytes=budget, chunk=3).run(reqs, realtime=False)
     assert len(rep.jobs) == 10 and ex.peak_total <= budget
     assert ex.trims >= 1                                 # released when admission was blocked
+    for j in rep.jobs:
+        np.testing.assert_array_equal(j.result, solo(j.req))
+
+
+def test_fifo_latencies_follow_the_single_server_queue():
+    # arrivals 0, 1, 1.5, 10 with solve times 2, 1, 0.5, 1: starts 0, 2, 3, 10 (the server is
+    # idle from 3.5 to 10), finishes 2, 3, 3.5, 11
+    reqs = [inputs.Request(rid=i, eq="nls", n=8, steps=1, arrival_s=a)
+            for i, a in enumerate([0.0, 1.0, 1.5, 10.0])]
+    lat = fifo_latencies(reqs[::-1], {0: 2.0, 1: 1.0, 2: 0.5, 3: 1.0})
+    assert lat == pytest.approx({0: 2.0, 1: 2.0, 2: 2.0, 3: 1.0})
+
+
+class StepRecorder(OracleExecutor):
+    def __init__(self):
+        super().__init__(delay=0.005)
+        self.steps = []
+
+    def advance(self, work):
+        self.steps.append({st["req"].rid: k for st, k in work})
+        return super().advance(work)
+
+
+def test_age_weighted_chunks_grow_with_waiting_and_keep_results():
+    # with age_s far below a round's duration, a request that has waited
+    # advances by several chunks per round (capped by max_boost and by its
+    # remaining steps); the results stay those of solo runs
+    reqs = [inputs.Request(0, "nls", 16, 30, 0.0), inputs.Request(1, "sg", 16, 9, 0.0),
+            inputs.Request(2, "ns", 16, 5, 0.0)]
+    ex = StepRecorder()
+    rep = Server(ex, budget_bytes=10 ** 9, chunk=2, age_s=1e-4, max_boost=4).run(reqs, realtime=True)
+    assert max(k for call in ex.steps for k in call.values()) == 8      # chunk x max_boost
+    assert all(k <= 8 for call in ex.steps for k in call.values())
+    assert sum(call.get(0, 0) for call in ex.steps) == 30
     for j in rep.jobs:
         np.testing.assert_array_equal(j.result, solo(j.req))
