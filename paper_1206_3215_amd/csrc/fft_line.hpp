@@ -253,11 +253,12 @@ __host__ __device__ __forceinline__ cpx<T> tw_load(const cpx<T>* tw, int len, un
 // Double-precision radix-16 stages after the first read three table
 // entries per butterfly, the powers 1, 4 and 8 of its base twiddle
 // c = exp(-2 pi i k / (16 Ns)), and form the other twelve powers by complex
-// products (at most three products deep, a few units of 2^-53): fifteen
-// table loads per butterfly cost more time than the products.  These loads
-// are issued before the preceding exchange, so their latency hides behind
-// it.  Single precision reads all fifteen entries, each rounded once, which
-// keeps the magnitude error of every twiddle at one rounding.
+// products (c^15 = c^8 (c^4 (c^2 c)) is four products deep: a few units of
+// 2^-53): fifteen table loads per butterfly cost more time than the
+// products.  These loads are issued before the preceding exchange, so their
+// latency hides behind it.  Single precision reads all fifteen entries:
+// each is the float pair of modulus closest to 1 near the exact value, and
+// products of such pairs would lose that.
 template <typename T>
 __host__ __device__ constexpr bool derived_twiddles(int r) {
   return r == 16 && std::is_same<T, double>::value;
