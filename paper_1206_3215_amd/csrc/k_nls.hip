@@ -19,7 +19,6 @@
 // v + v (E - 1) keeps |E| = 1 to within rounding of the small correction;
 // rounded (cos, -sin) pairs carry a bias of |E| near 1 for the energetic
 // low modes that would drain or feed the mass at every step.
-#include <cstdlib>
 #include "kernels.hpp"
 #include "launch.hpp"
 
@@ -117,10 +116,9 @@ __global__ __launch_bounds__((PairGeom<T, N, VPT, SPLIT, P_>::THREADS)) void k_n
 template <typename T, int N, int WT, int VPT, bool SPLIT, int WPE, int R>
 __global__ __launch_bounds__((WT * (N / VPT))) __attribute__((amdgpu_waves_per_eu(WPE))) void k_nls_col(
     FieldRef psi, int nx, int tiles_per_field, const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ ex,
-    const cpx<T>* __restrict__ ey, T scale, int stag, int nph, int first) {
+    const cpx<T>* __restrict__ ey, T scale) {
   using G = ColGeom<T, N, WT, VPT, SPLIT>;
   extern __shared__ char smem[];
-
   const int c = threadIdx.x % WT, t = threadIdx.x / WT;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int fld = tile / tiles_per_field;
@@ -157,11 +155,6 @@ __global__ __launch_bounds__((WT * (N / VPT))) __attribute__((amdgpu_waves_per_e
   if (valid) {
 #pragma unroll
     for (int s = 0; s < G::R; ++s) fb.st(voff(s), soff(s), v[s]);
-  }
-  {
-    const int k = (int)blockIdx.x < first ? ((int)blockIdx.x >> 3) % nph : 0;
-    const int n = __builtin_amdgcn_readfirstlane(k * stag);
-    for (int i = 0; i < n; ++i) __builtin_amdgcn_s_sleep(127);
   }
 }
 
@@ -310,12 +303,8 @@ static hipError_t col(int ny, int nx, int nfields, FieldRef psi, const void* tw,
       const int tiles = (nx + C::w - 1) / C::w;
       auto* k = &k_nls_col<T, N, C::w, C::vpt, C::split, C::wpe, C::radix>;
       allow_lds(k, G::LDS_BYTES);
-      const char* e1 = getenv("PST_STAG");
-      const char* e2 = getenv("PST_NPH");
-      const char* e3 = getenv("PST_FIRST");
       hipLaunchKernelGGL(k, dim3(tiles * nfields), dim3(G::THREADS), G::LDS_BYTES, s, psi, nx, tiles,
-                         (const cpx<T>*)tw, (const cpx<T>*)ex, (const cpx<T>*)ey, (T)(1.0 / ((double)nx * N)),
-                         e1 ? atoi(e1) : 0, e2 ? atoi(e2) : 4, e3 ? atoi(e3) : 256);
+                         (const cpx<T>*)tw, (const cpx<T>*)ex, (const cpx<T>*)ey, (T)(1.0 / ((double)nx * N)));
     });
   });
   return ok ? hipGetLastError() : hipErrorInvalidValue;
