@@ -288,9 +288,11 @@ pst_status pst_column_variant_info(pst_prec prec, int n, int variant, int single
 pst_status pst_row_variant_info(pst_prec prec, int n, int variant, int* pairs_per_block,
                                 int* values_per_thread, int* split, int* radix);
 
-/* Autotuning: times the column pass of equation eq on this plan in each
- * column variant, and for NLS the in-place row pass in each row variant, on
- * workspace data; keeps the fastest in the plan and remembers them for
+/* Autotuning: times, on workspace data, the in-place row pass in each row
+ * variant (NLS) and then the column pass of equation eq in each column
+ * variant (for NLS one row pass in the chosen row variant and one column
+ * pass per timed launch), each as the best of three windows of about 1 ms
+ * of launches; keeps the fastest in the plan and remembers them for
  * later plans of the same (eq, precision, nx, ny) in this process, so that
  * every plan of that class runs the same variants.  Synchronises.  *chosen
  * (may be NULL) receives the column variant. */
