@@ -10,7 +10,7 @@ from tests.gpuutil import need_gpu, rel_err, to_dev, to_host
 pytestmark = pytest.mark.gpu
 
 SHAPES = [(4, 4, 1), (8, 16, 2), (16, 8, 1), (32, 64, 3), (64, 64, 1), (128, 32, 2), (256, 512, 1),
-          (1024, 1024, 1), (2048, 64, 1), (64, 4096, 1), (4096, 4096, 1), (8192, 16, 1)]
+          (1024, 1024, 1), (2048, 64, 1), (64, 4096, 1), (4096, 4096, 1), (8192, 16, 1), (16, 8192, 1)]
 # relative error per log2(points): FP32 at its rounding level; FP64 at 5x the largest error
 # measured (4.3e-17 per log2 at 4096^2, as large as numpy's own FP64 round trip), the
 # O(eps log N) level of a double-precision FFT
