@@ -32,7 +32,9 @@ def test_served_results_equal_alone_and_oracle(fp64, tol):
     assert {r.eq for r in reqs} == {"nls", "sg", "ns"}
     ex = GpuExecutor(fp64=fp64)
     budget = 6 * 40 * 256 * 256 * (2 if fp64 else 1)      # admission binds
-    rep = Server(ex, budget_bytes=budget, chunk=16).run(reqs, realtime=True)
+    # FP32 runs the age-weighted rounds the bench serves with (chunks grow with waiting)
+    rep = Server(ex, budget_bytes=budget, chunk=16, age_s=None if fp64 else 0.01, max_boost=4).run(
+        reqs, realtime=True)
     _, _, alone, _ = fifo_baseline(reqs, fp64=fp64)
     assert len(rep.jobs) == len(reqs)
     worst = {}
